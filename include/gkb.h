@@ -1,0 +1,191 @@
+/*
+ * gkb.h -- C-ABI of the MI355X (gfx950) generalized Golub-Kahan
+ * bidiagonalization solver for MAC-discretized Stokes saddle-point systems
+ *
+ *     [[W, A], [A^T, 0]] [w; p] = [g; r]                                  (1)
+ *
+ * (Kruse, Sosonkina, Arioli, Tardieu, Ruede, "Parallel solution of saddle
+ * point systems with nested iterative solvers based on the Golub-Kahan
+ * Bidiagonalization": Section 1 for (1), Section 2 for the augmented
+ * Lagrangian M = W + gamma A N^-1 A^T and the transformation to g = 0,
+ * Section 2.1 Algorithm 1 for the recurrence, Section 2.2 for the delayed
+ * lower-bound stopping rule, Section 3 for the option set nu/delay/tol/maxit/
+ * monitor, Section 4.1.3 for the inner/outer tolerance policy.)
+ *
+ * Discretization.  Uniform MAC grid with cell size h.  W is the component-wise
+ * viscous operator -div(mu grad u_c) in strong-form scaling (entries ~ mu/h^2),
+ * A the cell-to-face gradient (entries +-1/h), A^T = -div its transpose.
+ * N = (1/eta) I: eta > 0 selects gamma = 1 (M = W + eta A A^T), eta = 0 selects
+ * gamma = 0, N = I (M = W), exactly as the paper's nu option.
+ *
+ * Memory layout (all solve vectors are DEVICE pointers, FP64, caller owned):
+ *   velocity-shaped (g, w):  full-face, component-major structure of arrays
+ *       u[nz][ny][nx+1], then v[nz][ny+1][nx], then (3D) w[nz+1][ny][nx],
+ *       x fastest; 2D grids use nz = 1 and have no w block.
+ *   pressure-shaped (r, p):  cells [nz][ny][nx].
+ * Faces normal to a DIRICHLET side are not unknowns: they are ignored on input
+ * and written as 0 on output; so is the pinned pressure cell.  Boundary data
+ * (inflow profiles, moving lids) must already be folded into g and r.
+ *
+ * Streams.  All device work of a context runs on the HIP stream given in
+ * gkb_options.hip_stream (NULL = the null stream).  Calls return after that
+ * stream's work for the call has completed.  A context is not thread-safe;
+ * use one context per stream.
+ *
+ * Errors.  Every entry point returns GKB_OK (0), GKB_MAXIT (1: result valid
+ * but the stopping rule was not met) or a negative code; gkb_strerror()
+ * describes it.  On a negative code output buffers hold unspecified values.
+ */
+#ifndef GKB_H
+#define GKB_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define GKB_OK 0
+#define GKB_MAXIT 1      /* outer maxit reached: the last iterate is returned */
+#define GKB_EINVAL (-1)  /* invalid argument */
+#define GKB_ENOMEM (-2)  /* device or host allocation failed, or workspace cap */
+#define GKB_EHIP (-3)    /* a HIP runtime call failed */
+#define GKB_ENAN (-4)    /* non-finite alpha, beta or residual */
+#define GKB_EINNER (-5)  /* an inner solve hit inner_maxit */
+
+/* boundary types of the six sides -x, +x, -y, +y, -z, +z */
+#define GKB_DIRICHLET 0  /* no-slip wall: wall-normal faces are not unknowns */
+#define GKB_NATURAL 1    /* do-nothing outflow: wall-normal faces are unknowns
+                            owning half a control volume */
+
+/* precision of the inner solves */
+#define GKB_FP64 0       /* everything in FP64 */
+#define GKB_MIXED 1      /* FP32 inner PCG / FCG and multigrid, FP64 GKB
+                            recurrence, FP64 coarsest solve, FP64 residual */
+
+/* inner solver for M x = f */
+#define GKB_INNER_JACOBI 0   /* Jacobi-preconditioned CG */
+#define GKB_INNER_MG 1       /* CG preconditioned by one geometric multigrid
+                                V(nu_pre, nu_post) cycle, weighted Jacobi smoother */
+#define GKB_INNER_LEARNED 2  /* flexible CG, preconditioner = V-cycle + CNN
+                                correction, falling back to MG-PCG */
+
+typedef struct {
+  int dim;       /* 2 or 3 */
+  int n[3];      /* cells per axis (n[2] ignored in 2D) */
+  double h;      /* cell size (> 0) */
+  int bc[6];     /* GKB_DIRICHLET / GKB_NATURAL for -x,+x,-y,+y,-z,+z */
+  int pin_cell;  /* flat cell index whose pressure is fixed to 0, or -1 */
+} gkb_grid;
+
+typedef struct {
+  int precision;        /* GKB_FP64 or GKB_MIXED */
+  int inner;            /* GKB_INNER_JACOBI / _MG / _LEARNED */
+  int mg_levels;        /* number of grid levels; 0 = coarsen while every n is
+                           even and > 8 */
+  int nu_pre, nu_post;  /* smoothing sweeps of the V-cycle */
+  double inner_tol;     /* relative residual of each inner solve (tau_in) */
+  int inner_maxit;
+  int maxit;            /* maximum number of GKB steps (zeta values) per sweep */
+  double refine_tol;    /* 0: one GKB run (the paper's method).  > 0: repeat
+                           GKB on the FP64 saddle residual (defect correction)
+                           until ||res|| <= refine_tol ||[g; r]|| */
+  int max_sweeps;       /* cap on defect-correction sweeps */
+  int check_every;      /* inner iterations between host convergence checks */
+  int use_graphs;       /* capture inner iterations in HIP graphs (1) or not */
+  void *hip_stream;     /* hipStream_t; NULL = null stream */
+  size_t max_workspace_bytes; /* 0 = unlimited; else setup fails with
+                                 GKB_ENOMEM above this device footprint */
+} gkb_options;
+
+typedef struct {
+  int sweeps;             /* GKB runs in the last solve */
+  int outer_iterations;   /* K summed over sweeps */
+  long inner_iterations;  /* inner Krylov iterations summed over all solves */
+  int inner_solves;
+  int fallbacks;          /* learned -> MG-PCG switches */
+  double residual;        /* final ||res||_2 / ||[g; r]||_2 (FP64), -1 if not computed */
+  double error_estimate;  /* last lower-bound ratio */
+  double seconds_solve;   /* wall time of the last gkb_solve */
+  int history_len;        /* entries valid in the two arrays below */
+  double zeta[512];       /* zeta_1..zeta_K of the last sweep (monitor) */
+  double estimate[512];   /* lower-bound ratio after each step (-1 before d+1) */
+  size_t workspace_bytes; /* device memory held by the context */
+  int mg_levels;          /* levels actually used */
+  double omega[16];       /* Jacobi weight per level */
+} gkb_stats_t;
+
+typedef struct gkb_ctx gkb_ctx;
+
+/* Fill *opt with defaults: FP64, MG inner, auto levels, V(2,2),
+   inner_tol 1e-10, inner_maxit 10000, maxit 500, refine_tol 0,
+   max_sweeps 10, check_every 8, graphs on, null stream. */
+void gkb_default_options(gkb_options *opt);
+
+/* Create a context for one grid, viscosity field and eta (the paper's nu).
+   viscosity: HOST pointer to n_cells doubles (> 0), or NULL for mu = 1; it is
+   copied.  opt may be NULL (defaults).  Allocates all device workspace,
+   builds the multigrid hierarchy (coarsened viscosity, Jacobi weights, dense
+   FP64 inverse of the coarsest operator).  Errors: GKB_EINVAL (dim not 2/3,
+   n < 2, h <= 0, eta < 0, bad bc, pin out of range, grid not divisible for
+   mg_levels, M singular because every side is NATURAL), GKB_ENOMEM, GKB_EHIP. */
+int gkb_setup(const gkb_grid *grid, const double *viscosity, double eta,
+              const gkb_options *opt, gkb_ctx **out);
+
+/* Solve (1) for the right-hand sides g (faces) and r (cells), all device FP64.
+   tol = tau of the lower-bound rule (Section 2.2; stop when the ratio of the
+   newest delay+1 squared zeta values to all of them is <= tol^2; tol <= 0 runs
+   maxit steps).  delay = d >= 0.  Writes w (faces) and p (cells); iterations
+   (may be NULL) receives K of the last sweep, error_estimate (may be NULL)
+   the last lower-bound ratio.  g and w, r and p may not alias.
+   Returns GKB_OK, GKB_MAXIT, GKB_ENAN, GKB_EINNER, GKB_EINVAL, GKB_EHIP. */
+int gkb_solve(gkb_ctx *c, const double *g, const double *r, double tol, int delay,
+              double *w, double *p, int *iterations, double *error_estimate);
+
+/* Statistics of the last gkb_solve (and setup facts). */
+int gkb_stats(const gkb_ctx *c, gkb_stats_t *out);
+
+/* Unknown-face / cell counts and full array sizes of the context's grid. */
+int gkb_sizes(const gkb_ctx *c, long *m_full, long *n_cells, long *m_unknown,
+              long *n_unknown);
+
+const char *gkb_strerror(int code);
+
+void gkb_destroy(gkb_ctx *c);
+
+/* ---- operator-level entry points (used by the parity tests) ----------- */
+
+#define GKB_OP_W 0   /* y = W x        (faces -> faces) */
+#define GKB_OP_A 1   /* y = A x        (cells -> faces) */
+#define GKB_OP_AT 2  /* y = A^T x      (faces -> cells) */
+#define GKB_OP_M 3   /* y = W x + eta A A^T x (faces -> faces) */
+#define GKB_OP_DIAG 4 /* y = diag(M)   (x ignored) */
+
+/* y = op(x) on the finest grid, in FP64 (precision = GKB_FP64; x, y double*)
+   or FP32 (precision = GKB_MIXED; x, y float*).  Device pointers. */
+int gkb_apply(gkb_ctx *c, int op, int precision, const void *x, void *y);
+
+/* One preconditioner application z = B r on the finest grid (B = one
+   V-cycle, or diag(M)^-1 for the Jacobi inner solver), FP64 or FP32 as
+   gkb_apply.  Device pointers. */
+int gkb_precondition(gkb_ctx *c, int precision, const void *r, void *z);
+
+/* Inner solve M x = f with the context's inner solver (x0 = 0), FP64 device
+   vectors (MIXED precision casts to FP32 internally).  tol <= 0 uses
+   inner_tol.  *iterations receives the iteration count.  Returns GKB_OK or
+   GKB_EINNER. */
+int gkb_inner_solve(gkb_ctx *c, const double *f, double *x, double tol,
+                    int *iterations);
+
+/* FP64 saddle residual res_w = g - W w - A p, res_r = r - A^T w (device);
+   norms (host, 4 doubles): ||[res_w; res_r]||, ||res_w||, ||res_r||,
+   ||[g; r]||.  res_w / res_r may be NULL when only the norms are wanted. */
+int gkb_residual(gkb_ctx *c, const double *g, const double *r, const double *w,
+                 const double *p, double *res_w, double *res_r, double *norms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GKB_H */

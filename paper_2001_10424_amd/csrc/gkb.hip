@@ -1,0 +1,1111 @@
+// Host runtime and C-ABI of the GKB solver (see include/gkb.h).
+//
+// Structure of one gkb_solve (paper Section 2, Algorithm 1):
+//   transformation  ghat = g + eta A r ; w0 = M^-1 ghat ; b = r - A^T w0
+//   initialisation  beta_1 = ||b||_{N^-1}, q_1 = N^-1 b / beta_1,
+//                   s = M^-1 A q_1, alpha_1 = ||s||_M, ...
+//   loop            t = N^-1 A^T v - alpha q, beta = ||t||_N, q = t / beta,
+//                   s = M^-1 (A q - beta M v), alpha = ||s||_M,
+//                   zeta = -(beta/alpha) zeta, d = (q - beta d)/alpha,
+//                   u += zeta v, p -= zeta d, lower-bound test with delay d.
+// The scalars of the outer recurrence live on the host in FP64; every vector
+// operation is a HIP kernel.  The inner solves M x = f (the dominant cost)
+// are PCG / flexible CG iterations whose scalars stay on the device; chunks
+// of iterations are captured in HIP graphs and replayed until the device-side
+// convergence flag is set (iterations after convergence are no-ops).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/gkb.h"
+#include "kernels.hpp"
+#include "learned.hpp"
+
+using namespace gkb;
+
+#define HIPCK(expr)                                                     \
+  do {                                                                  \
+    hipError_t e_ = (expr);                                             \
+    if (e_ != hipSuccess) {                                             \
+      std::fprintf(stderr, "gkb: HIP error %s at %s:%d\n",              \
+                   hipGetErrorString(e_), __FILE__, __LINE__);          \
+      return GKB_EHIP;                                                  \
+    }                                                                   \
+  } while (0)
+
+#define CK(expr)                  \
+  do {                            \
+    int rc_ = (expr);             \
+    if (rc_ < 0) return rc_;      \
+  } while (0)
+
+namespace {
+
+constexpr int kMaxLevels = 16;
+constexpr int kSlots = 6;
+
+int vec_blocks(int n) { return std::max(1, std::min((n + 1023) / 1024, 4096)); }
+
+struct FaceLaunch {
+  dim3 grid;
+  int kz = 1, zchunks = 1, nparts = 0;
+};
+
+FaceLaunch face_launch(const Grid& g, int kz) {
+  FaceLaunch L;
+  int maxplane = 0;
+  for (int c = 0; c < g.dim; ++c) maxplane = std::max(maxplane, g.ext[c][0] * g.ext[c][1]);
+  L.kz = kz;
+  L.zchunks = (g.nze + kz - 1) / kz;
+  L.grid = dim3((maxplane + kBlock - 1) / kBlock, 1, g.dim * L.zchunks);
+  L.nparts = L.grid.x * L.grid.z;
+  return L;
+}
+
+dim3 cell_grid(const Grid& g) {
+  return dim3((g.n[0] * g.n[1] + kBlock - 1) / kBlock, 1, g.n[2]);
+}
+int cell_parts(const Grid& g) { return cell_grid(g).x * g.n[2]; }
+
+dim3 transfer_grid(const Grid& g) {
+  int maxplane = 0;
+  for (int c = 0; c < g.dim; ++c) maxplane = std::max(maxplane, g.ext[c][0] * g.ext[c][1]);
+  return dim3((maxplane + kBlock - 1) / kBlock, 1, g.dim * g.nze);
+}
+
+template <typename T>
+struct DevArr {
+  T* p = nullptr;
+};
+
+struct Alloc {
+  std::vector<void*> ptrs;
+  size_t bytes = 0;
+  size_t cap = 0;
+  int get(void** out, size_t b) {
+    if (cap && bytes + b > cap) return GKB_ENOMEM;
+    void* q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(b, 256)) != hipSuccess) return GKB_ENOMEM;
+    ptrs.push_back(q);
+    bytes += b;
+    *out = q;
+    return GKB_OK;
+  }
+  template <typename T>
+  int arr(T** out, size_t n) {
+    return get(reinterpret_cast<void**>(out), n * sizeof(T));
+  }
+  void release() {
+    for (void* q : ptrs) (void)hipFree(q);
+    ptrs.clear();
+    bytes = 0;
+  }
+};
+
+// coefficient arrays of one level in one precision
+template <typename T>
+struct Coef {
+  T* mu = nullptr;
+  T* mue[3] = {nullptr, nullptr, nullptr};
+};
+
+template <typename T>
+struct Level {
+  Grid g;
+  Op<T> op;
+  T *b = nullptr, *x = nullptr, *t = nullptr, *rb = nullptr;
+  double omega = 0.8;
+  FaceLaunch fl;
+};
+
+template <typename T>
+struct Inner {
+  bool ready = false;
+  std::vector<Level<T>> lv;
+  T *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *dinv = nullptr;
+  T *rprev = nullptr;  // flexible CG
+  PcgState* st = nullptr;
+  hipGraphExec_t graph = nullptr;
+  int graph_len = 0;
+  int graph_mode = -1;
+};
+
+}  // namespace
+
+struct gkb_ctx {
+  Grid g;
+  double eta = 0.0;
+  gkb_options opt;
+  hipStream_t us = nullptr;  // caller stream (may be null)
+  hipStream_t cs = nullptr;  // own non-blocking stream
+  hipEvent_t ev = nullptr;
+  bool varmu = false;
+  Alloc mem;
+  int L = 1;
+  std::vector<Grid> grids;
+  std::vector<Coef<double>> coef64;
+  std::vector<Coef<float>> coef32;
+  std::vector<double> omega;
+  Op<double> op64;  // finest FP64 M
+  Op<float> op32;
+  double* Minv = nullptr;
+  int mc = 0;
+  Inner<double> in64;
+  Inner<float> in32;
+  // GKB vectors
+  double *ghat = nullptr, *w0 = nullptr, *u = nullptr, *v = nullptr, *Mv = nullptr, *s = nullptr,
+         *y = nullptr, *f = nullptr, *rw = nullptr, *dw = nullptr;
+  double *b = nullptr, *q = nullptr, *d = nullptr, *t = nullptr, *rr = nullptr, *dp = nullptr;
+  double* part[kSlots] = {nullptr};
+  int maxparts = 0;
+  double* dscal = nullptr;
+  double* hbuf = nullptr;  // pinned host
+  FaceLaunch fl0;
+  gkb_stats_t stats;
+  Learned* learned = nullptr;
+};
+
+namespace {
+
+// ------------------------------------------------------------ launches
+
+template <typename T, int MODE>
+void face_op(gkb_ctx* c, const Op<T>& op, const FaceLaunch& fl, const T* x, const T* b, T* y,
+             T omega, double* partial, const PcgState* st) {
+  const bool vm = op.mu != nullptr;
+  const int kz = fl.kz, zc = fl.zchunks;
+  hipStream_t s = c->cs;
+  if (op.g.dim == 2) {
+    if (vm) k_face_op<T, 2, true, MODE><<<fl.grid, kBlock, 0, s>>>(op, x, b, y, omega, kz, zc, partial, st);
+    else k_face_op<T, 2, false, MODE><<<fl.grid, kBlock, 0, s>>>(op, x, b, y, omega, kz, zc, partial, st);
+  } else {
+    if (vm) k_face_op<T, 3, true, MODE><<<fl.grid, kBlock, 0, s>>>(op, x, b, y, omega, kz, zc, partial, st);
+    else k_face_op<T, 3, false, MODE><<<fl.grid, kBlock, 0, s>>>(op, x, b, y, omega, kz, zc, partial, st);
+  }
+}
+
+void grad_axpy(gkb_ctx* c, const double* q, const double* yv, double s1, double s2, double* out) {
+  const FaceLaunch& fl = c->fl0;
+  if (c->g.dim == 2)
+    k_grad_axpy<2><<<fl.grid, kBlock, 0, c->cs>>>(c->g, q, yv, s1, s2, out, fl.kz, fl.zchunks);
+  else
+    k_grad_axpy<3><<<fl.grid, kBlock, 0, c->cs>>>(c->g, q, yv, s1, s2, out, fl.kz, fl.zchunks);
+}
+
+template <typename T>
+void div_axpy(gkb_ctx* c, const Grid& g, const T* x, const T* z, double s1, double s2, T* t,
+              double* partial, double* zz) {
+  if (g.dim == 2)
+    k_div_axpy<T, 2><<<cell_grid(g), kBlock, 0, c->cs>>>(g, x, z, s1, s2, t, partial, zz);
+  else
+    k_div_axpy<T, 3><<<cell_grid(g), kBlock, 0, c->cs>>>(g, x, z, s1, s2, t, partial, zz);
+}
+
+int host_sum(gkb_ctx* c, const double* partial, int n, double* out) {
+  k_sum_partials<<<1, kFinal, 0, c->cs>>>(partial, n, c->dscal);
+  HIPCK(hipMemcpyAsync(c->hbuf, c->dscal, sizeof(double), hipMemcpyDeviceToHost, c->cs));
+  HIPCK(hipStreamSynchronize(c->cs));
+  *out = c->hbuf[0];
+  return GKB_OK;
+}
+
+// ---------------------------------------------------------- multigrid
+
+template <typename T>
+void vcycle(gkb_ctx* c, Inner<T>& in, int l, const T* b, T* x, double* dot_partial,
+            const PcgState* st) {
+  Level<T>& L = in.lv[l];
+  hipStream_t s = c->cs;
+  if (l == c->L - 1) {
+    const int m = L.g.m_full;
+    k_coarse_gemv<T><<<(m + 3) / 4, kBlock, m * sizeof(double), s>>>(m, c->Minv, b, x, st);
+    if (dot_partial) {
+      k_dot<T><<<vec_blocks(m), kBlock, 0, s>>>(m, b, x, dot_partial);
+    }
+    return;
+  }
+  const int n1 = c->opt.nu_pre, n2 = c->opt.nu_post, tot = n1 + n2;
+  const T om = T(L.omega);
+  // sweep k writes x when (tot - k) is even, else t
+  auto dst = [&](int k) { return ((tot - k) % 2 == 0) ? x : L.t; };
+  const T* cur = nullptr;
+  int k = 0;
+  if (n1 > 0) {
+    ++k;
+    T* o = dst(k);
+    face_op<T, kJacobi0>(c, L.op, L.fl, nullptr, b, o, om, nullptr, st);
+    cur = o;
+    for (int i = 1; i < n1; ++i) {
+      ++k;
+      T* o2 = dst(k);
+      face_op<T, kJacobi>(c, L.op, L.fl, cur, b, o2, om, nullptr, st);
+      cur = o2;
+    }
+  }
+  Level<T>& Lc = in.lv[l + 1];
+  const dim3 tg = transfer_grid(Lc.g);
+  if (cur) {
+    face_op<T, kResid>(c, L.op, L.fl, cur, b, L.rb, T(0), nullptr, st);
+    if (L.g.dim == 2) k_restrict<T, 2><<<tg, kBlock, 0, s>>>(L.g, Lc.g, L.rb, Lc.b, st);
+    else k_restrict<T, 3><<<tg, kBlock, 0, s>>>(L.g, Lc.g, L.rb, Lc.b, st);
+  } else {
+    if (L.g.dim == 2) k_restrict<T, 2><<<tg, kBlock, 0, s>>>(L.g, Lc.g, b, Lc.b, st);
+    else k_restrict<T, 3><<<tg, kBlock, 0, s>>>(L.g, Lc.g, b, Lc.b, st);
+  }
+  vcycle<T>(c, in, l + 1, Lc.b, Lc.x, nullptr, st);
+  // prolongate into the current iterate (or into a zeroed x when no pre-smoothing)
+  T* it = const_cast<T*>(cur);
+  if (!it) {
+    it = (n2 % 2 == 0) ? x : L.t;
+    k_fill<T><<<vec_blocks(L.g.m_full), kBlock, 0, s>>>(L.g.m_full, T(0), it);
+  }
+  const dim3 fg = transfer_grid(L.g);
+  if (L.g.dim == 2) k_prolong_add<T, 2><<<fg, kBlock, 0, s>>>(L.g, Lc.g, Lc.x, it, st);
+  else k_prolong_add<T, 3><<<fg, kBlock, 0, s>>>(L.g, Lc.g, Lc.x, it, st);
+  cur = it;
+  for (int i = 0; i < n2; ++i) {
+    ++k;
+    T* o = (cur == x) ? L.t : x;
+    const bool last = (i == n2 - 1);
+    if (last && dot_partial)
+      face_op<T, kJacobiDot>(c, L.op, L.fl, cur, b, o, om, dot_partial, st);
+    else
+      face_op<T, kJacobi>(c, L.op, L.fl, cur, b, o, om, nullptr, st);
+    cur = o;
+  }
+  if (cur != x) {
+    k_cast<T, T><<<vec_blocks(L.g.m_full), kBlock, 0, s>>>(L.g.m_full, cur, x);
+  }
+  if (n2 == 0 && dot_partial) {
+    k_dot<T><<<vec_blocks(L.g.m_full), kBlock, 0, s>>>(L.g.m_full, b, x, dot_partial);
+  }
+}
+
+template <typename T>
+int vcycle_parts(gkb_ctx* c, Inner<T>& in) {
+  if (c->L == 1) return vec_blocks(in.lv[0].g.m_full);
+  if (c->opt.nu_post == 0) return vec_blocks(in.lv[0].g.m_full);
+  return in.lv[0].fl.nparts;
+}
+
+// -------------------------------------------------------------- PCG
+
+template <typename T>
+Inner<T>& inner_of(gkb_ctx* c);
+template <>
+Inner<double>& inner_of<double>(gkb_ctx* c) { return c->in64; }
+template <>
+Inner<float>& inner_of<float>(gkb_ctx* c) { return c->in32; }
+
+template <typename T>
+const Op<T>& op_of(gkb_ctx* c);
+template <>
+const Op<double>& op_of<double>(gkb_ctx* c) { return c->op64; }
+template <>
+const Op<float>& op_of<float>(gkb_ctx* c) { return c->op32; }
+
+template <typename T>
+void pcg_iterations(gkb_ctx* c, Inner<T>& in, int count) {
+  const Level<T>& L0 = in.lv[0];
+  const int n = L0.g.m_full, vb = vec_blocks(n);
+  hipStream_t s = c->cs;
+  const bool jac = c->opt.inner == GKB_INNER_JACOBI;
+  for (int it = 0; it < count; ++it) {
+    face_op<T, kApplyDot>(c, L0.op, L0.fl, in.p, nullptr, in.q, T(0), c->part[0], in.st);
+    k_pcg_alpha<<<1, kFinal, 0, s>>>(in.st, c->part[0], L0.fl.nparts);
+    if (jac) {
+      k_pcg_xr<T><<<vb, kBlock, 0, s>>>(n, in.st, in.p, in.q, in.x, in.r, in.dinv, in.z,
+                                        c->part[1], c->part[2]);
+      k_pcg_check<<<1, kFinal, 0, s>>>(in.st, c->part[1], vb, c->part[2], vb);
+    } else {
+      k_pcg_xr<T><<<vb, kBlock, 0, s>>>(n, in.st, in.p, in.q, in.x, in.r, nullptr, nullptr,
+                                        c->part[1], nullptr);
+      k_pcg_check<<<1, kFinal, 0, s>>>(in.st, c->part[1], vb, nullptr, 0);
+      vcycle<T>(c, in, 0, in.r, in.z, c->part[2], in.st);
+      k_pcg_beta<<<1, kFinal, 0, s>>>(in.st, c->part[2], vcycle_parts<T>(c, in));
+    }
+    k_pcg_p<T><<<vb, kBlock, 0, s>>>(n, in.st, in.z, in.p);
+  }
+}
+
+template <typename T>
+int ensure_graph(gkb_ctx* c, Inner<T>& in, int count) {
+  if (in.graph && in.graph_len == count && in.graph_mode == c->opt.inner) return GKB_OK;
+  if (in.graph) {
+    (void)hipGraphExecDestroy(in.graph);
+    in.graph = nullptr;
+  }
+  hipGraph_t gr;
+  HIPCK(hipStreamBeginCapture(c->cs, hipStreamCaptureModeThreadLocal));
+  pcg_iterations<T>(c, in, count);
+  HIPCK(hipStreamEndCapture(c->cs, &gr));
+  HIPCK(hipGraphInstantiate(&in.graph, gr, nullptr, nullptr, 0));
+  (void)hipGraphDestroy(gr);
+  in.graph_len = count;
+  in.graph_mode = c->opt.inner;
+  return GKB_OK;
+}
+
+// x_out = M^-1 f (FP64 in and out; T = working precision of the inner solve)
+template <typename T>
+int inner_solve(gkb_ctx* c, const double* f, double* x_out, double tol, int* iters) {
+  Inner<T>& in = inner_of<T>(c);
+  if (!in.ready) return GKB_EINVAL;
+  if (c->opt.inner == GKB_INNER_LEARNED && c->learned && learned_enabled(c->learned))
+    return learned_solve<T>(c, f, x_out, tol, iters);
+  const Level<T>& L0 = in.lv[0];
+  const int n = L0.g.m_full, vb = vec_blocks(n);
+  hipStream_t s = c->cs;
+  k_pcg_init<double, T><<<vb, kBlock, 0, s>>>(n, f, in.x, in.r, c->part[3]);
+  if (c->opt.inner == GKB_INNER_JACOBI) {
+    k_pcg_p0<T><<<vb, kBlock, 0, s>>>(n, in.dinv, in.r, in.z, in.p, c->part[2]);
+  } else {
+    vcycle<T>(c, in, 0, in.r, in.z, nullptr, nullptr);
+    k_pcg_p0<T><<<vb, kBlock, 0, s>>>(n, nullptr, in.r, in.z, in.p, c->part[2]);
+  }
+  k_pcg_start<<<1, kFinal, 0, s>>>(in.st, c->part[3], vb, c->part[2], vb, tol, c->opt.inner_maxit);
+  const int chunk = std::max(1, c->opt.check_every);
+  if (c->opt.use_graphs) CK(ensure_graph<T>(c, in, chunk));
+  PcgState hs;
+  for (;;) {
+    if (c->opt.use_graphs) {
+      HIPCK(hipGraphLaunch(in.graph, s));
+    } else {
+      pcg_iterations<T>(c, in, chunk);
+    }
+    HIPCK(hipMemcpyAsync(c->hbuf, in.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    std::memcpy(&hs, c->hbuf, sizeof(PcgState));
+    if (hs.done) break;
+  }
+  k_cast<T, double><<<vb, kBlock, 0, s>>>(n, in.x, x_out);
+  if (iters) *iters = hs.it;
+  c->stats.inner_iterations += hs.it;
+  c->stats.inner_solves += 1;
+  if (hs.nonfinite) return GKB_ENAN;
+  if (hs.status == -5) return GKB_EINNER;
+  return GKB_OK;
+}
+
+int inner_solve_any(gkb_ctx* c, const double* f, double* x, double tol, int* iters) {
+  if (c->opt.precision == GKB_MIXED) return inner_solve<float>(c, f, x, tol, iters);
+  return inner_solve<double>(c, f, x, tol, iters);
+}
+
+// ---------------------------------------------------------------- GKB
+
+// One GKB run (Algorithm 1 with the transformation of Section 2) for the
+// right-hand sides (gv, rv); writes w, p.
+int gkb_run(gkb_ctx* c, const double* gv, const double* rv, double tol, int delay, double* w,
+            double* p, int* K_out, double* est_out) {
+  const Grid& G = c->g;
+  const int m = G.m_full, nc = G.n_cells, vbm = vec_blocks(m), vbc = vec_blocks(nc);
+  hipStream_t s = c->cs;
+  const double eta = c->eta;
+  const double ninv = eta > 0.0 ? eta : 1.0;
+  const double itol = c->opt.inner_tol;
+  int its = 0;
+  // ghat = g + gamma A N^-1 r (masked)
+  grad_axpy(c, rv, gv, eta, 1.0, c->ghat);
+  k_dot<double><<<vbm, kBlock, 0, s>>>(m, c->ghat, c->ghat, c->part[0]);
+  double gg = 0.0;
+  CK(host_sum(c, c->part[0], vbm, &gg));
+  if (!std::isfinite(gg)) return GKB_ENAN;
+  if (gg == 0.0) {
+    k_fill<double><<<vbm, kBlock, 0, s>>>(m, 0.0, c->w0);
+  } else {
+    CK(inner_solve_any(c, c->ghat, c->w0, itol, &its));
+  }
+  // b = r - A^T w0, beta_1 = sqrt(b . N^-1 b)
+  div_axpy<double>(c, G, c->w0, rv, -1.0, 1.0, c->b, c->part[0], nullptr);
+  double bb = 0.0;
+  CK(host_sum(c, c->part[0], cell_parts(G), &bb));
+  const double beta1 = std::sqrt(ninv * bb);
+  if (!std::isfinite(beta1)) return GKB_ENAN;
+  k_fill<double><<<vbc, kBlock, 0, s>>>(nc, 0.0, p);
+  k_fill<double><<<vbc, kBlock, 0, s>>>(nc, 0.0, c->d);
+  k_fill<double><<<vbm, kBlock, 0, s>>>(m, 0.0, c->u);
+  c->stats.history_len = 0;
+  if (beta1 == 0.0) {
+    k_cast<double, double><<<vbm, kBlock, 0, s>>>(m, c->w0, w);
+    HIPCK(hipStreamSynchronize(s));
+    if (K_out) *K_out = 0;
+    if (est_out) *est_out = 0.0;
+    c->stats.error_estimate = 0.0;
+    return GKB_OK;
+  }
+  // q_1 = N^-1 b / beta_1
+  k_cast<double, double><<<vbc, kBlock, 0, s>>>(nc, c->b, c->q);
+  k_axpby<<<vbc, kBlock, 0, s>>>(nc, 0.0, c->q, ninv / beta1, c->q);
+  std::vector<double> zs;
+  double zeta = 0.0, alpha = 0.0, beta = 0.0, sum_all = 0.0, est = 1.0;
+  int status = GKB_MAXIT;
+  for (int K = 0; K < c->opt.maxit; ++K) {
+    if (K == 0) {
+      grad_axpy(c, c->q, nullptr, 1.0, 0.0, c->f);  // f = A q_1
+    } else {
+      // t = N^-1 A^T v - alpha q ; beta = ||t||_N
+      div_axpy<double>(c, G, c->v, c->q, ninv, -alpha, c->t, c->part[0], nullptr);
+      double tt = 0.0;
+      CK(host_sum(c, c->part[0], cell_parts(G), &tt));
+      beta = std::sqrt(tt / ninv);
+      if (!std::isfinite(beta)) return GKB_ENAN;
+      if (beta <= 1e-13 * alpha) {  // breakdown: Krylov space exhausted
+        est = 0.0;
+        status = GKB_OK;
+        break;
+      }
+      k_cast<double, double><<<vbc, kBlock, 0, s>>>(nc, c->t, c->q);
+      k_axpby<<<vbc, kBlock, 0, s>>>(nc, 0.0, c->q, 1.0 / beta, c->q);
+      grad_axpy(c, c->q, c->Mv, 1.0, -beta, c->f);  // f = A q - beta M v
+    }
+    CK(inner_solve_any(c, c->f, c->s, itol, &its));
+    // y = M s, alpha = sqrt(s . M s)
+    face_op<double, kApplyDot>(c, c->op64, c->fl0, c->s, nullptr, c->y, 0.0, c->part[0], nullptr);
+    double sMs = 0.0;
+    CK(host_sum(c, c->part[0], c->fl0.nparts, &sMs));
+    alpha = std::sqrt(sMs);
+    if (!std::isfinite(alpha) || alpha == 0.0) return GKB_ENAN;
+    zeta = (K == 0) ? beta1 / alpha : -(beta / alpha) * zeta;
+    k_gkb_faces<<<vbm, kBlock, 0, s>>>(m, 1.0 / alpha, zeta, c->s, c->y, c->v, c->Mv, c->u);
+    k_gkb_cells<<<vbc, kBlock, 0, s>>>(nc, 1.0 / alpha, K == 0 ? 0.0 : beta, zeta, c->q, c->d, p);
+    zs.push_back(zeta);
+    sum_all += zeta * zeta;
+    const int Kn = K + 1;
+    double e_now = -1.0;
+    if (Kn >= delay + 1) {
+      double win = 0.0;
+      for (int j = Kn - delay; j <= Kn; ++j) win += zs[j - 1] * zs[j - 1];
+      est = std::sqrt(win / sum_all);
+      e_now = est;
+    }
+    if (Kn <= 512) {
+      c->stats.zeta[Kn - 1] = zeta;
+      c->stats.estimate[Kn - 1] = e_now;
+      c->stats.history_len = Kn;
+    }
+    if (e_now >= 0.0 && tol > 0.0 && est <= tol) {
+      status = GKB_OK;
+      break;
+    }
+  }
+  // w = u + w0 (non-unknown faces are zero in both)
+  k_cast<double, double><<<vbm, kBlock, 0, s>>>(m, c->u, w);
+  k_axpby<<<vbm, kBlock, 0, s>>>(m, 1.0, c->w0, 1.0, w);
+  HIPCK(hipStreamSynchronize(s));
+  if (K_out) *K_out = (int)zs.size();
+  if (est_out) *est_out = est;
+  c->stats.outer_iterations += (int)zs.size();
+  c->stats.error_estimate = est;
+  return status;
+}
+
+int residual_impl(gkb_ctx* c, const double* gv, const double* rv, const double* w, const double* p,
+                  double* res_w, double* res_r, double* norms) {
+  const Grid& G = c->g;
+  Op<double> opW = c->op64;
+  opW.eta = 0.0;
+  const FaceLaunch& fl = c->fl0;
+  hipStream_t s = c->cs;
+  const bool vm = opW.mu != nullptr;
+  if (G.dim == 2) {
+    if (vm) k_resid_w<2, true><<<fl.grid, kBlock, 0, s>>>(opW, gv, w, p, res_w, fl.kz, fl.zchunks, c->part[0], c->part[1]);
+    else k_resid_w<2, false><<<fl.grid, kBlock, 0, s>>>(opW, gv, w, p, res_w, fl.kz, fl.zchunks, c->part[0], c->part[1]);
+  } else {
+    if (vm) k_resid_w<3, true><<<fl.grid, kBlock, 0, s>>>(opW, gv, w, p, res_w, fl.kz, fl.zchunks, c->part[0], c->part[1]);
+    else k_resid_w<3, false><<<fl.grid, kBlock, 0, s>>>(opW, gv, w, p, res_w, fl.kz, fl.zchunks, c->part[0], c->part[1]);
+  }
+  div_axpy<double>(c, G, w, rv, -1.0, 1.0, res_r ? res_r : c->t, c->part[2], c->part[3]);
+  double rw = 0, ggw = 0, rrr = 0, rr2 = 0;
+  CK(host_sum(c, c->part[0], fl.nparts, &rw));
+  CK(host_sum(c, c->part[1], fl.nparts, &ggw));
+  CK(host_sum(c, c->part[2], cell_parts(G), &rrr));
+  CK(host_sum(c, c->part[3], cell_parts(G), &rr2));
+  norms[0] = std::sqrt(rw + rrr);
+  norms[1] = std::sqrt(rw);
+  norms[2] = std::sqrt(rrr);
+  norms[3] = std::sqrt(ggw + rr2);
+  return GKB_OK;
+}
+
+// ------------------------------------------------------------- setup
+
+void edge_viscosity(const Grid& g, const std::vector<double>& mu, int B, std::vector<double>& out) {
+  int ex[3];
+  for (int a = 0; a < 3; ++a) ex[a] = g.n[a] + (a != B ? 1 : 0);
+  if (g.dim == 2) ex[2] = 1;
+  out.assign((size_t)ex[0] * ex[1] * ex[2], 0.0);
+  for (int k = 0; k < ex[2]; ++k)
+    for (int j = 0; j < ex[1]; ++j)
+      for (int i = 0; i < ex[0]; ++i) {
+        const int E[3] = {i, j, k};
+        double sum = 0.0;
+        int cnt = 0;
+        // cells touching the edge: along axes != B the two cells E-1, E
+        int lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+          if (a == B || (g.dim == 2 && a == 2)) {
+            lo[a] = hi[a] = E[a];
+          } else {
+            lo[a] = E[a] - 1;
+            hi[a] = E[a];
+          }
+        }
+        for (int kk = lo[2]; kk <= hi[2]; ++kk)
+          for (int jj = lo[1]; jj <= hi[1]; ++jj)
+            for (int ii = lo[0]; ii <= hi[0]; ++ii) {
+              if (ii < 0 || jj < 0 || kk < 0 || ii >= g.n[0] || jj >= g.n[1] || kk >= g.n[2])
+                continue;
+              sum += mu[((size_t)kk * g.n[1] + jj) * g.n[0] + ii];
+              ++cnt;
+            }
+        out[((size_t)k * ex[1] + j) * ex[0] + i] = cnt ? sum / cnt : 1.0;
+      }
+}
+
+template <typename T>
+int upload(gkb_ctx* c, const std::vector<double>& h, T** out) {
+  std::vector<T> tmp(h.begin(), h.end());
+  CK(c->mem.arr(out, tmp.size()));
+  HIPCK(hipMemcpy(*out, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice));
+  return GKB_OK;
+}
+
+template <typename T>
+Op<T> make_op(const Grid& g, double eta, const Coef<T>& cf, bool varmu) {
+  Op<T> op;
+  op.g = g;
+  op.eta = T(eta);
+  op.ih2 = T(1.0 / (g.h * g.h));
+  op.ih = T(1.0 / g.h);
+  op.mu = varmu ? cf.mu : nullptr;
+  for (int b = 0; b < 3; ++b) op.mue[b] = varmu ? cf.mue[b] : nullptr;
+  return op;
+}
+
+// Cholesky-based inverse of an SPD matrix (row-major, in place); false if
+// not positive definite
+bool spd_inverse(std::vector<double>& A, int n) {
+  std::vector<double> L((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    const double* Lj = &L[(size_t)j * n];
+    double dsum = A[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) dsum -= Lj[k] * Lj[k];
+    if (!(dsum > 0.0)) return false;
+    const double ljj = std::sqrt(dsum);
+    L[(size_t)j * n + j] = ljj;
+    for (int i = j + 1; i < n; ++i) {
+      const double* Li = &L[(size_t)i * n];
+      double sum = A[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) sum -= Li[k] * Lj[k];
+      L[(size_t)i * n + j] = sum / ljj;
+    }
+  }
+  // X = L^-1 (lower triangular), by forward substitution on columns
+  std::vector<double> X((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    const double* Li = &L[(size_t)i * n];
+    double* Xi = &X[(size_t)i * n];
+    Xi[i] = 1.0 / Li[i];
+    for (int k = 0; k < i; ++k) {
+      // X[i][k] = -(sum_{l=k}^{i-1} L[i][l] X[l][k]) / L[i][i]
+      double sum = 0.0;
+      for (int l = k; l < i; ++l) sum += Li[l] * X[(size_t)l * n + k];
+      Xi[k] = -sum / Li[i];
+    }
+  }
+  // A^-1 = X^T X
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double sum = 0.0;
+      for (int k = i; k < n; ++k) sum += X[(size_t)k * n + i] * X[(size_t)k * n + j];
+      A[(size_t)i * n + j] = sum;
+      A[(size_t)j * n + i] = sum;
+    }
+  return true;
+}
+
+template <typename T>
+int build_inner(gkb_ctx* c, Inner<T>& in, const std::vector<Coef<T>>& coef) {
+  const int L = c->L;
+  in.lv.resize(L);
+  for (int l = 0; l < L; ++l) {
+    Level<T>& lv = in.lv[l];
+    lv.g = c->grids[l];
+    lv.op = make_op<T>(lv.g, c->eta, coef[l], c->varmu);
+    lv.omega = c->omega[l];
+    lv.fl = face_launch(lv.g, 4);
+    const int m = lv.g.m_full;
+    if (l > 0) {
+      CK(c->mem.arr(&lv.b, m));
+      CK(c->mem.arr(&lv.x, m));
+    }
+    CK(c->mem.arr(&lv.t, m));
+    CK(c->mem.arr(&lv.rb, m));
+  }
+  const int m = c->g.m_full;
+  CK(c->mem.arr(&in.x, m));
+  CK(c->mem.arr(&in.r, m));
+  CK(c->mem.arr(&in.z, m));
+  CK(c->mem.arr(&in.p, m));
+  CK(c->mem.arr(&in.q, m));
+  CK(c->mem.arr(&in.rprev, m));
+  CK(c->mem.arr(&in.st, 1));
+  // Jacobi preconditioner 1/diag(M) (0 at non-unknown faces)
+  CK(c->mem.arr(&in.dinv, m));
+  face_op<T, kDiag>(c, in.lv[0].op, in.lv[0].fl, nullptr, nullptr, in.dinv, T(0), nullptr, nullptr);
+  std::vector<T> dh(m);
+  HIPCK(hipMemcpyAsync(dh.data(), in.dinv, m * sizeof(T), hipMemcpyDeviceToHost, c->cs));
+  HIPCK(hipStreamSynchronize(c->cs));
+  for (auto& v : dh) v = v != T(0) ? T(1) / v : T(0);
+  HIPCK(hipMemcpy(in.dinv, dh.data(), m * sizeof(T), hipMemcpyHostToDevice));
+  in.ready = true;
+  return GKB_OK;
+}
+
+int setup_impl(gkb_ctx* c, const gkb_grid* grid, const double* visc, double eta,
+               const gkb_options* opt) {
+  c->opt = *opt;
+  c->eta = eta;
+  c->mem.cap = opt->max_workspace_bytes;
+  c->us = static_cast<hipStream_t>(opt->hip_stream);
+  HIPCK(hipStreamCreateWithFlags(&c->cs, hipStreamNonBlocking));
+  HIPCK(hipEventCreateWithFlags(&c->ev, hipEventDisableTiming));
+  int n[3] = {grid->n[0], grid->n[1], grid->dim == 3 ? grid->n[2] : 1};
+  c->g = make_grid(grid->dim, n, grid->h, grid->bc, grid->pin_cell);
+  c->varmu = visc != nullptr;
+  // levels
+  int L = opt->mg_levels;
+  if (opt->inner == GKB_INNER_JACOBI) L = 1;
+  if (L <= 0) {
+    L = 1;
+    int nn[3] = {n[0], n[1], n[2]};
+    for (;;) {
+      bool ok = true;
+      for (int a = 0; a < grid->dim; ++a) ok = ok && (nn[a] % 2 == 0) && (nn[a] > 8);
+      if (!ok || L >= kMaxLevels) break;
+      for (int a = 0; a < grid->dim; ++a) nn[a] /= 2;
+      ++L;
+    }
+  }
+  for (int l = 1; l < L; ++l)
+    for (int a = 0; a < grid->dim; ++a)
+      if ((n[a] >> (l - 1)) % 2 != 0 || (n[a] >> l) < 2) return GKB_EINVAL;
+  c->L = L;
+  std::vector<std::vector<double>> mus(L);
+  for (int l = 0; l < L; ++l) {
+    int nl[3] = {n[0] >> l, n[1] >> l, grid->dim == 3 ? (n[2] >> l) : 1};
+    int pin = -1;
+    if (grid->pin_cell >= 0) {
+      const int pi = grid->pin_cell % n[0], pj = (grid->pin_cell / n[0]) % n[1],
+                pk = grid->pin_cell / (n[0] * n[1]);
+      pin = ((pk >> l) * nl[1] + (pj >> l)) * nl[0] + (pi >> l);
+      if (grid->dim == 2) pin = (pj >> l) * nl[0] + (pi >> l);
+    }
+    c->grids.push_back(make_grid(grid->dim, nl, grid->h * (double)(1 << l), grid->bc, pin));
+    const Grid& g = c->grids.back();
+    mus[l].assign(g.n_cells, 1.0);
+    if (c->varmu) {
+      if (l == 0) {
+        std::memcpy(mus[0].data(), visc, sizeof(double) * g.n_cells);
+      } else {
+        const Grid& f = c->grids[l - 1];
+        const int dz = grid->dim == 3 ? 2 : 1;
+        for (int k = 0; k < g.n[2]; ++k)
+          for (int j = 0; j < g.n[1]; ++j)
+            for (int i = 0; i < g.n[0]; ++i) {
+              double s = 0;
+              for (int kk = 0; kk < dz; ++kk)
+                for (int jj = 0; jj < 2; ++jj)
+                  for (int ii = 0; ii < 2; ++ii)
+                    s += mus[l - 1][((size_t)(dz * k + kk) * f.n[1] + 2 * j + jj) * f.n[0] + 2 * i + ii];
+              mus[l][((size_t)k * g.n[1] + j) * g.n[0] + i] = s / (dz * 4);
+            }
+      }
+    }
+  }
+  c->coef64.resize(L);
+  c->coef32.resize(L);
+  if (c->varmu) {
+    for (int l = 0; l < L; ++l) {
+      const Grid& g = c->grids[l];
+      CK(upload<double>(c, mus[l], &c->coef64[l].mu));
+      CK(upload<float>(c, mus[l], &c->coef32[l].mu));
+      for (int b = 0; b < 3; ++b) {
+        if (g.dim == 2 && b != 2) continue;
+        std::vector<double> e;
+        edge_viscosity(g, mus[l], b, e);
+        CK(upload<double>(c, e, &c->coef64[l].mue[b]));
+        CK(upload<float>(c, e, &c->coef32[l].mue[b]));
+      }
+    }
+  }
+  c->op64 = make_op<double>(c->g, eta, c->coef64[0], c->varmu);
+  c->op32 = make_op<float>(c->g, eta, c->coef32[0], c->varmu);
+  c->fl0 = face_launch(c->g, 4);
+  // partial buffers: the largest reduction launch over all levels
+  int maxp = 0;
+  for (int l = 0; l < L; ++l) {
+    maxp = std::max(maxp, face_launch(c->grids[l], 4).nparts);
+    maxp = std::max(maxp, cell_parts(c->grids[l]));
+    maxp = std::max(maxp, vec_blocks(c->grids[l].m_full));
+  }
+  c->maxparts = maxp;
+  for (int i = 0; i < kSlots; ++i) CK(c->mem.arr(&c->part[i], maxp));
+  CK(c->mem.arr(&c->dscal, 8));
+  HIPCK(hipHostMalloc(reinterpret_cast<void**>(&c->hbuf), 4096, hipHostMallocDefault));
+  const int m = c->g.m_full, nc = c->g.n_cells;
+  double** fv[] = {&c->ghat, &c->w0, &c->u, &c->v, &c->Mv, &c->s, &c->y, &c->f, &c->rw, &c->dw};
+  for (auto pp : fv) CK(c->mem.arr(pp, m));
+  double** cv[] = {&c->b, &c->q, &c->d, &c->t, &c->rr, &c->dp};
+  for (auto pp : cv) CK(c->mem.arr(pp, nc));
+  // Jacobi weights by power iteration on D^-1 M_l (FP64), omega = 1.6 / (1.05 lambda)
+  c->omega.assign(L, 0.8);
+  for (int l = 0; l < L - (L > 1 ? 1 : 0); ++l) {
+    const Grid& g = c->grids[l];
+    Op<double> op = make_op<double>(g, eta, c->coef64[l], c->varmu);
+    FaceLaunch fl = face_launch(g, 4);
+    double *xa, *ya;
+    CK(c->mem.arr(&xa, g.m_full));
+    CK(c->mem.arr(&ya, g.m_full));
+    std::vector<double> x0(g.m_full);
+    unsigned s = 12345u;
+    for (auto& v : x0) {
+      s = s * 1664525u + 1013904223u;
+      v = 0.5 + (s >> 8) * (1.0 / 16777216.0);
+    }
+    HIPCK(hipMemcpy(xa, x0.data(), g.m_full * sizeof(double), hipMemcpyHostToDevice));
+    double lam = 1.0;
+    for (int it = 0; it < 40; ++it) {
+      face_op<double, kDinvM>(c, op, fl, xa, nullptr, ya, 0.0, c->part[0], nullptr);
+      double yy = 0.0;
+      k_dot<double><<<vec_blocks(g.m_full), kBlock, 0, c->cs>>>(g.m_full, xa, xa, c->part[1]);
+      double xx = 0.0;
+      CK(host_sum(c, c->part[0], fl.nparts, &yy));
+      CK(host_sum(c, c->part[1], vec_blocks(g.m_full), &xx));
+      lam = std::sqrt(yy / xx);
+      k_axpby<<<vec_blocks(g.m_full), kBlock, 0, c->cs>>>(g.m_full, 1.0 / std::sqrt(yy), ya, 0.0, xa);
+    }
+    c->omega[l] = 1.6 / (1.05 * lam);
+  }
+  // coarsest level: dense FP64 inverse of M on the unknown faces
+  if (opt->inner != GKB_INNER_JACOBI) {
+    const Grid& g = c->grids[L - 1];
+    const int mcf = g.m_full;
+    if (mcf > 4096) return GKB_EINVAL;  // coarsest grid too large for a dense solve
+    Op<double> op = make_op<double>(g, eta, c->coef64[L - 1], c->varmu);
+    FaceLaunch fl = face_launch(g, 4);
+    double *e, *col, *dg;
+    CK(c->mem.arr(&e, mcf));
+    CK(c->mem.arr(&col, mcf));
+    CK(c->mem.arr(&dg, mcf));
+    face_op<double, kDiag>(c, op, fl, nullptr, nullptr, dg, 0.0, nullptr, nullptr);
+    std::vector<double> dgh(mcf);
+    HIPCK(hipMemcpyAsync(dgh.data(), dg, mcf * sizeof(double), hipMemcpyDeviceToHost, c->cs));
+    HIPCK(hipStreamSynchronize(c->cs));
+    std::vector<int> idx;
+    for (int i = 0; i < mcf; ++i)
+      if (dgh[i] != 0.0) idx.push_back(i);
+    const int nu = (int)idx.size();
+    std::vector<double> Mfull((size_t)mcf * mcf);
+    std::vector<double> one(1, 1.0);
+    for (int jj = 0; jj < mcf; ++jj) {
+      if (dgh[jj] == 0.0) continue;
+      k_fill<double><<<vec_blocks(mcf), kBlock, 0, c->cs>>>(mcf, 0.0, e);
+      HIPCK(hipMemcpyAsync(e + jj, one.data(), sizeof(double), hipMemcpyHostToDevice, c->cs));
+      face_op<double, kApply>(c, op, fl, e, nullptr, col, 0.0, nullptr, nullptr);
+      HIPCK(hipMemcpyAsync(&Mfull[(size_t)jj * mcf], col, mcf * sizeof(double),
+                           hipMemcpyDeviceToHost, c->cs));
+    }
+    HIPCK(hipStreamSynchronize(c->cs));
+    std::vector<double> Mu((size_t)nu * nu);
+    for (int a = 0; a < nu; ++a)
+      for (int b2 = 0; b2 < nu; ++b2) Mu[(size_t)a * nu + b2] = Mfull[(size_t)idx[b2] * mcf + idx[a]];
+    if (!spd_inverse(Mu, nu)) return GKB_EINVAL;
+    std::vector<double> Minv((size_t)mcf * mcf, 0.0);
+    for (int a = 0; a < nu; ++a)
+      for (int b2 = 0; b2 < nu; ++b2) Minv[(size_t)idx[a] * mcf + idx[b2]] = Mu[(size_t)a * nu + b2];
+    CK(c->mem.arr(&c->Minv, (size_t)mcf * mcf));
+    HIPCK(hipMemcpy(c->Minv, Minv.data(), Minv.size() * sizeof(double), hipMemcpyHostToDevice));
+    c->mc = mcf;
+  }
+  if (opt->precision == GKB_MIXED) CK(build_inner<float>(c, c->in32, c->coef32));
+  else CK(build_inner<double>(c, c->in64, c->coef64));
+  if (opt->inner == GKB_INNER_LEARNED) CK(learned_create(c));
+  HIPCK(hipStreamSynchronize(c->cs));
+  c->stats = gkb_stats_t{};
+  return GKB_OK;
+}
+
+int validate(const gkb_grid* g, double eta, const gkb_options* o) {
+  if (!g || (g->dim != 2 && g->dim != 3)) return GKB_EINVAL;
+  if (!(g->h > 0.0) || !(eta >= 0.0) || !std::isfinite(eta)) return GKB_EINVAL;
+  long nc = 1;
+  for (int a = 0; a < g->dim; ++a) {
+    if (g->n[a] < 2) return GKB_EINVAL;
+    nc *= g->n[a];
+  }
+  if (nc > (1L << 30)) return GKB_EINVAL;
+  bool all_nat = true;
+  for (int s = 0; s < 2 * g->dim; ++s) {
+    if (g->bc[s] != GKB_DIRICHLET && g->bc[s] != GKB_NATURAL) return GKB_EINVAL;
+    all_nat = all_nat && g->bc[s] == GKB_NATURAL;
+  }
+  if (all_nat) return GKB_EINVAL;
+  if (g->pin_cell < -1 || g->pin_cell >= nc) return GKB_EINVAL;
+  if (o->precision != GKB_FP64 && o->precision != GKB_MIXED) return GKB_EINVAL;
+  if (o->inner < 0 || o->inner > 2) return GKB_EINVAL;
+  if (o->nu_pre < 0 || o->nu_post < 0 || o->nu_pre + o->nu_post < 1) return GKB_EINVAL;
+  if (o->inner_maxit < 1 || o->maxit < 1 || o->max_sweeps < 1) return GKB_EINVAL;
+  return GKB_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C-ABI
+
+extern "C" {
+
+void gkb_default_options(gkb_options* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->precision = GKB_FP64;
+  o->inner = GKB_INNER_MG;
+  o->mg_levels = 0;
+  o->nu_pre = 2;
+  o->nu_post = 2;
+  o->inner_tol = 1e-10;
+  o->inner_maxit = 10000;
+  o->maxit = 500;
+  o->refine_tol = 0.0;
+  o->max_sweeps = 10;
+  o->check_every = 8;
+  o->use_graphs = 1;
+  o->hip_stream = nullptr;
+  o->max_workspace_bytes = 0;
+}
+
+int gkb_setup(const gkb_grid* grid, const double* viscosity, double eta, const gkb_options* opt,
+              gkb_ctx** out) {
+  if (!out) return GKB_EINVAL;
+  *out = nullptr;
+  gkb_options o;
+  if (opt) o = *opt;
+  else gkb_default_options(&o);
+  int rc = validate(grid, eta, &o);
+  if (rc) return rc;
+  if (viscosity) {
+    long nc = (long)grid->n[0] * grid->n[1] * (grid->dim == 3 ? grid->n[2] : 1);
+    for (long i = 0; i < nc; ++i)
+      if (!(viscosity[i] > 0.0) || !std::isfinite(viscosity[i])) return GKB_EINVAL;
+  }
+  gkb_ctx* c = new (std::nothrow) gkb_ctx();
+  if (!c) return GKB_ENOMEM;
+  rc = setup_impl(c, grid, viscosity, eta, &o);
+  if (rc < 0) {
+    gkb_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return GKB_OK;
+}
+
+int gkb_solve(gkb_ctx* c, const double* g, const double* r, double tol, int delay, double* w,
+              double* p, int* iterations, double* error_estimate) {
+  if (!c || !g || !r || !w || !p || delay < 0) return GKB_EINVAL;
+  auto t0 = std::chrono::steady_clock::now();
+  HIPCK(hipEventRecord(c->ev, c->us));
+  HIPCK(hipStreamWaitEvent(c->cs, c->ev, 0));
+  c->stats.sweeps = 0;
+  c->stats.outer_iterations = 0;
+  c->stats.inner_iterations = 0;
+  c->stats.inner_solves = 0;
+  c->stats.fallbacks = 0;
+  c->stats.residual = -1.0;
+  int K = 0, rc;
+  double est = 0.0;
+  if (c->opt.refine_tol <= 0.0) {
+    rc = gkb_run(c, g, r, tol, delay, w, p, &K, &est);
+    c->stats.sweeps = 1;
+  } else {
+    // defect correction: (w, p) += GKB(res) until the FP64 residual is small
+    const int m = c->g.m_full, nc = c->g.n_cells;
+    k_fill<double><<<vec_blocks(m), kBlock, 0, c->cs>>>(m, 0.0, w);
+    k_fill<double><<<vec_blocks(nc), kBlock, 0, c->cs>>>(nc, 0.0, p);
+    double norms[4];
+    rc = GKB_MAXIT;
+    for (int sw = 0; sw <= c->opt.max_sweeps; ++sw) {
+      int r2 = residual_impl(c, g, r, w, p, c->rw, c->rr, norms);
+      if (r2 < 0) return r2;
+      const double rel = norms[3] > 0 ? norms[0] / norms[3] : 0.0;
+      c->stats.residual = rel;
+      if (!std::isfinite(rel)) {
+        rc = GKB_ENAN;
+        break;
+      }
+      if (rel <= c->opt.refine_tol) {
+        rc = GKB_OK;
+        break;
+      }
+      if (sw == c->opt.max_sweeps) break;
+      int r3 = gkb_run(c, c->rw, c->rr, tol, delay, c->dw, c->dp, &K, &est);
+      c->stats.sweeps += 1;
+      if (r3 < 0) {
+        rc = r3;
+        break;
+      }
+      k_axpby<<<vec_blocks(m), kBlock, 0, c->cs>>>(m, 1.0, c->dw, 1.0, w);
+      k_axpby<<<vec_blocks(nc), kBlock, 0, c->cs>>>(nc, 1.0, c->dp, 1.0, p);
+    }
+  }
+  HIPCK(hipStreamSynchronize(c->cs));
+  c->stats.seconds_solve =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (iterations) *iterations = K;
+  if (error_estimate) *error_estimate = est;
+  return rc;
+}
+
+int gkb_stats(const gkb_ctx* c, gkb_stats_t* out) {
+  if (!c || !out) return GKB_EINVAL;
+  *out = c->stats;
+  out->workspace_bytes = c->mem.bytes;
+  out->mg_levels = c->L;
+  for (int l = 0; l < c->L && l < 16; ++l) out->omega[l] = c->omega[l];
+  return GKB_OK;
+}
+
+int gkb_sizes(const gkb_ctx* c, long* m_full, long* n_cells, long* m_unknown, long* n_unknown) {
+  if (!c) return GKB_EINVAL;
+  const Grid& g = c->g;
+  if (m_full) *m_full = g.m_full;
+  if (n_cells) *n_cells = g.n_cells;
+  long mu = 0;
+  for (int cc = 0; cc < g.dim; ++cc) {
+    long plane = (long)g.ext[cc][0] * g.ext[cc][1] * g.ext[cc][2] / g.ext[cc][cc];
+    long cnt = g.ext[cc][cc];
+    if (g.bc[2 * cc] == GKB_DIRICHLET) --cnt;
+    if (g.bc[2 * cc + 1] == GKB_DIRICHLET) --cnt;
+    mu += plane * cnt;
+  }
+  if (m_unknown) *m_unknown = mu;
+  if (n_unknown) *n_unknown = g.n_cells - (g.pin >= 0 ? 1 : 0);
+  return GKB_OK;
+}
+
+const char* gkb_strerror(int code) {
+  switch (code) {
+    case GKB_OK: return "ok";
+    case GKB_MAXIT: return "maximum number of GKB iterations reached";
+    case GKB_EINVAL: return "invalid argument";
+    case GKB_ENOMEM: return "out of memory or workspace cap exceeded";
+    case GKB_EHIP: return "HIP runtime error";
+    case GKB_ENAN: return "non-finite value in the iteration";
+    case GKB_EINNER: return "inner solve did not converge within inner_maxit";
+    default: return "unknown error code";
+  }
+}
+
+void gkb_destroy(gkb_ctx* c) {
+  if (!c) return;
+  if (c->cs) (void)hipStreamSynchronize(c->cs);
+  if (c->in64.graph) (void)hipGraphExecDestroy(c->in64.graph);
+  if (c->in32.graph) (void)hipGraphExecDestroy(c->in32.graph);
+  if (c->learned) learned_destroy(c);
+  c->mem.release();
+  if (c->hbuf) (void)hipHostFree(c->hbuf);
+  if (c->ev) (void)hipEventDestroy(c->ev);
+  if (c->cs) (void)hipStreamDestroy(c->cs);
+  delete c;
+}
+
+int gkb_apply(gkb_ctx* c, int op, int precision, const void* x, void* y) {
+  if (!c || !y || (op != GKB_OP_DIAG && !x)) return GKB_EINVAL;
+  HIPCK(hipEventRecord(c->ev, c->us));
+  HIPCK(hipStreamWaitEvent(c->cs, c->ev, 0));
+  const Grid& G = c->g;
+  if (precision == GKB_FP64) {
+    const double* xd = static_cast<const double*>(x);
+    double* yd = static_cast<double*>(y);
+    Op<double> o = c->op64;
+    switch (op) {
+      case GKB_OP_W: o.eta = 0.0; face_op<double, kApply>(c, o, c->fl0, xd, nullptr, yd, 0.0, nullptr, nullptr); break;
+      case GKB_OP_M: face_op<double, kApply>(c, o, c->fl0, xd, nullptr, yd, 0.0, nullptr, nullptr); break;
+      case GKB_OP_DIAG: face_op<double, kDiag>(c, o, c->fl0, nullptr, nullptr, yd, 0.0, nullptr, nullptr); break;
+      case GKB_OP_A: grad_axpy(c, xd, nullptr, 1.0, 0.0, yd); break;
+      case GKB_OP_AT: div_axpy<double>(c, G, xd, nullptr, 1.0, 0.0, yd, nullptr, nullptr); break;
+      default: return GKB_EINVAL;
+    }
+  } else if (precision == GKB_MIXED) {
+    const float* xf = static_cast<const float*>(x);
+    float* yf = static_cast<float*>(y);
+    Op<float> o = c->op32;
+    switch (op) {
+      case GKB_OP_W: o.eta = 0.0f; face_op<float, kApply>(c, o, c->fl0, xf, nullptr, yf, 0.0f, nullptr, nullptr); break;
+      case GKB_OP_M: face_op<float, kApply>(c, o, c->fl0, xf, nullptr, yf, 0.0f, nullptr, nullptr); break;
+      case GKB_OP_DIAG: face_op<float, kDiag>(c, o, c->fl0, nullptr, nullptr, yf, 0.0f, nullptr, nullptr); break;
+      case GKB_OP_AT: div_axpy<float>(c, G, xf, nullptr, 1.0, 0.0, yf, nullptr, nullptr); break;
+      default: return GKB_EINVAL;
+    }
+  } else {
+    return GKB_EINVAL;
+  }
+  HIPCK(hipGetLastError());
+  HIPCK(hipStreamSynchronize(c->cs));
+  return GKB_OK;
+}
+
+int gkb_precondition(gkb_ctx* c, int precision, const void* r, void* z) {
+  if (!c || !r || !z) return GKB_EINVAL;
+  HIPCK(hipEventRecord(c->ev, c->us));
+  HIPCK(hipStreamWaitEvent(c->cs, c->ev, 0));
+  const int m = c->g.m_full;
+  if (precision == GKB_FP64) {
+    if (!c->in64.ready) return GKB_EINVAL;
+    Inner<double>& in = c->in64;
+    if (c->opt.inner == GKB_INNER_JACOBI)
+      k_pcg_p0<double><<<vec_blocks(m), kBlock, 0, c->cs>>>(m, in.dinv, static_cast<const double*>(r),
+                                                            static_cast<double*>(z), in.q, c->part[0]);
+    else
+      vcycle<double>(c, in, 0, static_cast<const double*>(r), static_cast<double*>(z), nullptr, nullptr);
+  } else if (precision == GKB_MIXED) {
+    if (!c->in32.ready) return GKB_EINVAL;
+    Inner<float>& in = c->in32;
+    if (c->opt.inner == GKB_INNER_JACOBI)
+      k_pcg_p0<float><<<vec_blocks(m), kBlock, 0, c->cs>>>(m, in.dinv, static_cast<const float*>(r),
+                                                           static_cast<float*>(z), in.q, c->part[0]);
+    else
+      vcycle<float>(c, in, 0, static_cast<const float*>(r), static_cast<float*>(z), nullptr, nullptr);
+  } else {
+    return GKB_EINVAL;
+  }
+  HIPCK(hipGetLastError());
+  HIPCK(hipStreamSynchronize(c->cs));
+  return GKB_OK;
+}
+
+int gkb_inner_solve(gkb_ctx* c, const double* f, double* x, double tol, int* iterations) {
+  if (!c || !f || !x) return GKB_EINVAL;
+  HIPCK(hipEventRecord(c->ev, c->us));
+  HIPCK(hipStreamWaitEvent(c->cs, c->ev, 0));
+  int rc = inner_solve_any(c, f, x, tol > 0 ? tol : c->opt.inner_tol, iterations);
+  HIPCK(hipStreamSynchronize(c->cs));
+  return rc;
+}
+
+int gkb_residual(gkb_ctx* c, const double* g, const double* r, const double* w, const double* p,
+                 double* res_w, double* res_r, double* norms) {
+  if (!c || !g || !r || !w || !p || !norms) return GKB_EINVAL;
+  HIPCK(hipEventRecord(c->ev, c->us));
+  HIPCK(hipStreamWaitEvent(c->cs, c->ev, 0));
+  return residual_impl(c, g, r, w, p, res_w, res_r, norms);
+}
+
+}  // extern "C"
+#include "learned_impl.hpp"

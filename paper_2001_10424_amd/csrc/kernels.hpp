@@ -1,0 +1,596 @@
+// HIP kernels for gfx950: MAC operators with fused reductions, BLAS-1
+// updates of the GKB recurrence and of PCG, multigrid transfers and the dense
+// FP64 coarsest-grid solve.
+//
+// Reductions are deterministic: each block reduces its values with a fixed
+// wave-shuffle tree and a fixed-order pass over the waves, writes one FP64
+// partial, and a one-block kernel sums the partials in a fixed order.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "mac.hpp"
+
+namespace gkb {
+
+constexpr int kBlock = 256;   // threads per block (4 wave64)
+constexpr int kFinal = 1024;  // threads of the one-block finalisers
+
+// ------------------------------------------------------------- reductions
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// block-wide sum, result valid in thread 0; fixed order
+template <int BS>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < BS / 64; ++w) s += sh[w];
+  }
+  return s;
+}
+
+// Sum of n partials in a fixed order (one block of kFinal threads).
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int n, double* sh) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += kFinal) v += part[i];
+  double s = block_sum<kFinal>(v, sh);
+  return s;  // valid in thread 0
+}
+
+__global__ __launch_bounds__(kFinal) void k_sum_partials(const double* part, int n, double* out) {
+  __shared__ double sh[kFinal / 64];
+  double s = sum_partials(part, n, sh);
+  if (threadIdx.x == 0) *out = s;
+}
+
+// ------------------------------------------------------------ PCG state
+
+struct PcgState {
+  double rz, pq, alpha, beta, rr, rr0, tol2;
+  double rz_prev;  // flexible CG
+  int it, maxit, done, status, nonfinite, pad;
+};
+
+// ------------------------------------------------- face-operator kernels
+
+enum MMode {
+  kApply = 0,      // y = M x
+  kApplyDot = 1,   // y = M x, partial x.y
+  kJacobi = 2,     // y = x + omega (b - M x) / D
+  kJacobiDot = 3,  // y = x + omega (b - M x) / D, partial b.y
+  kResid = 4,      // y = b - M x
+  kDinvM = 5,      // y = (M x) / D, partial y.y
+  kJacobi0 = 6,    // y = omega b / D   (first sweep from a zero guess)
+  kDiag = 7,       // y = D
+  kResidDot = 8    // y = b - M x, partial y.y
+};
+
+// Thread mapping: blockIdx.z = component * zchunks + z-chunk; each block
+// covers kBlock consecutive (x fastest) faces of one z-plane of that
+// component's array and loops over kz consecutive planes.
+template <typename T, int DIM, bool VARMU, int MODE, int C>
+__device__ __forceinline__ double face_op(const Op<T>& op, const T* __restrict__ x,
+                                          const T* __restrict__ b, T* __restrict__ y, T omega,
+                                          int idx, int k0, int kz) {
+  const Grid& G = op.g;
+  const int e0 = G.ext[C][0], e1 = G.ext[C][1], e2 = G.ext[C][2];
+  double part = 0.0;
+  if (idx >= e0 * e1) return part;
+  const int j = idx / e0, i = idx - j * e0;
+  const int ic_fixed = C == 0 ? i : (C == 1 ? j : -1);
+  for (int k = k0; k < k0 + kz && k < e2; ++k) {
+    const int ic = C == 2 ? k : ic_fixed;
+    const int f = fidx<C>(G, i, j, k);
+    if (!unk<C>(G, ic)) {
+      y[f] = T(0);
+      continue;
+    }
+    if (MODE == kJacobi0 || MODE == kDiag) {
+      const T d = diag_M<T, DIM, VARMU, C>(op, i, j, k);
+      y[f] = MODE == kDiag ? d : omega * b[f] / d;
+      continue;
+    }
+    T mx, d;
+    stencil_M<T, DIM, VARMU, C>(op, x, i, j, k, mx, d);
+    T out;
+    if (MODE == kApply || MODE == kApplyDot) {
+      out = mx;
+      if (MODE == kApplyDot) part += double(x[f]) * double(out);
+    } else if (MODE == kJacobi || MODE == kJacobiDot) {
+      const T bf = b[f];
+      out = x[f] + omega * (bf - mx) / d;
+      if (MODE == kJacobiDot) part += double(bf) * double(out);
+    } else if (MODE == kResid || MODE == kResidDot) {
+      out = b[f] - mx;
+      if (MODE == kResidDot) part += double(out) * double(out);
+    } else {  // kDinvM
+      out = mx / d;
+      part += double(out) * double(out);
+    }
+    y[f] = out;
+  }
+  return part;
+}
+
+template <typename T, int DIM, bool VARMU, int MODE>
+__global__ __launch_bounds__(kBlock) void k_face_op(Op<T> op, const T* __restrict__ x,
+                                                    const T* __restrict__ b, T* __restrict__ y,
+                                                    T omega, int kz, int zchunks,
+                                                    double* __restrict__ partial,
+                                                    const PcgState* __restrict__ st) {
+  if (st && st->done) return;
+  const int c = blockIdx.z / zchunks;
+  const int k0 = (blockIdx.z - c * zchunks) * kz;
+  const int idx = blockIdx.x * kBlock + threadIdx.x;
+  double part = 0.0;
+  if (c == 0) part = face_op<T, DIM, VARMU, MODE, 0>(op, x, b, y, omega, idx, k0, kz);
+  else if (c == 1) part = face_op<T, DIM, VARMU, MODE, 1>(op, x, b, y, omega, idx, k0, kz);
+  else if (DIM == 3) part = face_op<T, DIM, VARMU, MODE, 2>(op, x, b, y, omega, idx, k0, kz);
+  constexpr bool kRed = MODE == kApplyDot || MODE == kJacobiDot || MODE == kDinvM || MODE == kResidDot;
+  if (kRed) {
+    __shared__ double sh[kBlock / 64];
+    double s = block_sum<kBlock>(part, sh);
+    if (threadIdx.x == 0) partial[blockIdx.z * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// out = s1 * (A q) + s2 * yv on unknown faces (yv may be null), 0 elsewhere
+template <typename T, int C>
+__device__ __forceinline__ void grad_face(const Grid& G, const T* __restrict__ q,
+                                          const double* __restrict__ yv, double s1, double s2,
+                                          double ih, double* __restrict__ out, int idx, int k0,
+                                          int kz) {
+  const int e0 = G.ext[C][0], e1 = G.ext[C][1], e2 = G.ext[C][2];
+  if (idx >= e0 * e1) return;
+  const int j = idx / e0, i = idx - j * e0;
+  for (int k = k0; k < k0 + kz && k < e2; ++k) {
+    const int ic = C == 0 ? i : (C == 1 ? j : k);
+    const int f = fidx<C>(G, i, j, k);
+    if (!unk<C>(G, ic)) {
+      out[f] = 0.0;
+      continue;
+    }
+    double v = s1 * double(grad_f<C>(G, q, i, j, k)) * ih;
+    if (yv) v += s2 * yv[f];
+    out[f] = v;
+  }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_grad_axpy(Grid G, const double* __restrict__ q,
+                                                      const double* __restrict__ yv, double s1,
+                                                      double s2, double* __restrict__ out, int kz,
+                                                      int zchunks) {
+  const int c = blockIdx.z / zchunks;
+  const int k0 = (blockIdx.z - c * zchunks) * kz;
+  const int idx = blockIdx.x * kBlock + threadIdx.x;
+  const double ih = 1.0 / G.h;
+  if (c == 0) grad_face<double, 0>(G, q, yv, s1, s2, ih, out, idx, k0, kz);
+  else if (c == 1) grad_face<double, 1>(G, q, yv, s1, s2, ih, out, idx, k0, kz);
+  else if (DIM == 3) grad_face<double, 2>(G, q, yv, s1, s2, ih, out, idx, k0, kz);
+}
+
+// t = s1 * (A^T x) + s2 * z on unpinned cells (z may be null), 0 at the pin;
+// partial t.t and, if zz_partial, z.z over unpinned cells
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_div_axpy(Grid G, const T* __restrict__ x,
+                                                     const T* __restrict__ z, double s1, double s2,
+                                                     T* __restrict__ t, double* __restrict__ partial,
+                                                     double* __restrict__ zz_partial) {
+  const int nxy = G.n[0] * G.n[1];
+  const int k = blockIdx.z;
+  const int idx = blockIdx.x * kBlock + threadIdx.x;
+  double a = 0.0, bz = 0.0;
+  if (idx < nxy) {
+    const int j = idx / G.n[0], i = idx - j * G.n[0];
+    const int cc = cidx(G, i, j, k);
+    double v = 0.0;
+    if (cc != G.pin) {
+      v = s1 * double(cdiv<DIM>(G, x, i, j, k)) / G.h;
+      if (z) {
+        const double zv = double(z[cc]);
+        v += s2 * zv;
+        bz = zv * zv;
+      }
+    }
+    t[cc] = T(v);
+    a = v * v;
+  }
+  __shared__ double sh[kBlock / 64];
+  double s = block_sum<kBlock>(a, sh);
+  if (threadIdx.x == 0 && partial) partial[blockIdx.z * gridDim.x + blockIdx.x] = s;
+  if (zz_partial) {
+    __syncthreads();
+    double s2v = block_sum<kBlock>(bz, sh);
+    if (threadIdx.x == 0) zz_partial[blockIdx.z * gridDim.x + blockIdx.x] = s2v;
+  }
+}
+
+// FP64 velocity residual res = g - W w - A p on unknown faces; partials of
+// res.res and g.g (unknown faces)
+template <int DIM, bool VARMU, int C>
+__device__ __forceinline__ void resid_face(const Op<double>& op, const double* __restrict__ g,
+                                           const double* __restrict__ w,
+                                           const double* __restrict__ p, double* __restrict__ res,
+                                           int idx, int k0, int kz, double& rr, double& gg) {
+  const Grid& G = op.g;
+  const int e0 = G.ext[C][0], e1 = G.ext[C][1], e2 = G.ext[C][2];
+  if (idx >= e0 * e1) return;
+  const int j = idx / e0, i = idx - j * e0;
+  for (int k = k0; k < k0 + kz && k < e2; ++k) {
+    const int ic = C == 0 ? i : (C == 1 ? j : k);
+    const int f = fidx<C>(G, i, j, k);
+    if (!unk<C>(G, ic)) {
+      if (res) res[f] = 0.0;
+      continue;
+    }
+    double mx, d;
+    stencil_M<double, DIM, VARMU, C>(op, w, i, j, k, mx, d);
+    const double gf = g[f];
+    const double v = gf - mx - grad_f<C>(G, p, i, j, k) * op.ih;
+    if (res) res[f] = v;
+    rr += v * v;
+    gg += gf * gf;
+  }
+}
+
+template <int DIM, bool VARMU>
+__global__ __launch_bounds__(kBlock) void k_resid_w(Op<double> op, const double* __restrict__ g,
+                                                    const double* __restrict__ w,
+                                                    const double* __restrict__ p,
+                                                    double* __restrict__ res, int kz, int zchunks,
+                                                    double* __restrict__ part_rr,
+                                                    double* __restrict__ part_gg) {
+  const int c = blockIdx.z / zchunks;
+  const int k0 = (blockIdx.z - c * zchunks) * kz;
+  const int idx = blockIdx.x * kBlock + threadIdx.x;
+  double rr = 0.0, gg = 0.0;
+  if (c == 0) resid_face<DIM, VARMU, 0>(op, g, w, p, res, idx, k0, kz, rr, gg);
+  else if (c == 1) resid_face<DIM, VARMU, 1>(op, g, w, p, res, idx, k0, kz, rr, gg);
+  else if (DIM == 3) resid_face<DIM, VARMU, 2>(op, g, w, p, res, idx, k0, kz, rr, gg);
+  __shared__ double sh[kBlock / 64];
+  double s = block_sum<kBlock>(rr, sh);
+  if (threadIdx.x == 0) part_rr[blockIdx.z * gridDim.x + blockIdx.x] = s;
+  __syncthreads();
+  s = block_sum<kBlock>(gg, sh);
+  if (threadIdx.x == 0) part_gg[blockIdx.z * gridDim.x + blockIdx.x] = s;
+}
+
+// --------------------------------------------------------- vector kernels
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(int n, T v, T* __restrict__ y) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) y[i] = v;
+}
+
+// y = a x + b y
+__global__ __launch_bounds__(kBlock) void k_axpby(int n, double a, const double* __restrict__ x,
+                                                  double b, double* __restrict__ y) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+    y[i] = a * x[i] + b * y[i];
+}
+
+// partial x.y
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dot(int n, const T* __restrict__ x,
+                                                const T* __restrict__ y, double* __restrict__ partial) {
+  double s = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+    s += double(x[i]) * double(y[i]);
+  __shared__ double sh[kBlock / 64];
+  s = block_sum<kBlock>(s, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kBlock) void k_cast(int n, const TI* __restrict__ x, TO* __restrict__ y) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) y[i] = TO(x[i]);
+}
+
+// GKB face update: v = s/alpha, Mv = y/alpha, u += zeta v
+__global__ __launch_bounds__(kBlock) void k_gkb_faces(int n, double ialpha, double zeta,
+                                                      const double* __restrict__ s,
+                                                      const double* __restrict__ yv,
+                                                      double* __restrict__ v, double* __restrict__ Mv,
+                                                      double* __restrict__ u) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const double vi = s[i] * ialpha;
+    v[i] = vi;
+    Mv[i] = yv[i] * ialpha;
+    u[i] += zeta * vi;
+  }
+}
+
+// GKB cell update: d = (q - beta d)/alpha, p -= zeta d
+__global__ __launch_bounds__(kBlock) void k_gkb_cells(int n, double ialpha, double beta, double zeta,
+                                                      const double* __restrict__ q,
+                                                      double* __restrict__ d, double* __restrict__ p) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const double di = (q[i] - beta * d[i]) * ialpha;
+    d[i] = di;
+    p[i] -= zeta * di;
+  }
+}
+
+// --------------------------------------------------------------- PCG
+
+// x = 0, r = f (cast), partial f.f
+template <typename TI, typename T>
+__global__ __launch_bounds__(kBlock) void k_pcg_init(int n, const TI* __restrict__ f,
+                                                     T* __restrict__ x, T* __restrict__ r,
+                                                     double* __restrict__ part_ff) {
+  double s = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const T fi = T(f[i]);
+    x[i] = T(0);
+    r[i] = fi;
+    s += double(fi) * double(fi);
+  }
+  __shared__ double sh[kBlock / 64];
+  s = block_sum<kBlock>(s, sh);
+  if (threadIdx.x == 0) part_ff[blockIdx.x] = s;
+}
+
+// z = dinv r (Jacobi) when dinv != null; p = z; partial r.z
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pcg_p0(int n, const T* __restrict__ dinv,
+                                                   const T* __restrict__ r, T* __restrict__ z,
+                                                   T* __restrict__ p, double* __restrict__ part_rz) {
+  double s = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const T ri = r[i];
+    const T zi = dinv ? dinv[i] * ri : z[i];
+    if (dinv) z[i] = zi;
+    p[i] = zi;
+    s += double(ri) * double(zi);
+  }
+  __shared__ double sh[kBlock / 64];
+  s = block_sum<kBlock>(s, sh);
+  if (threadIdx.x == 0) part_rz[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kFinal) void k_pcg_start(PcgState* st, const double* part_ff, int nff,
+                                                      const double* part_rz, int nrz, double tol,
+                                                      int maxit) {
+  __shared__ double sh[kFinal / 64];
+  const double ff = sum_partials(part_ff, nff, sh);
+  __syncthreads();
+  const double rz = sum_partials(part_rz, nrz, sh);
+  if (threadIdx.x == 0) {
+    st->rr0 = ff;
+    st->rr = ff;
+    st->rz = rz;
+    st->tol2 = tol * tol;
+    st->it = 0;
+    st->maxit = maxit;
+    st->alpha = st->beta = st->pq = 0.0;
+    st->rz_prev = rz;
+    st->nonfinite = 0;
+    st->done = (ff == 0.0) ? 1 : 0;
+    st->status = 0;
+  }
+}
+
+__global__ __launch_bounds__(kFinal) void k_pcg_alpha(PcgState* st, const double* part_pq, int n) {
+  if (st->done) return;
+  __shared__ double sh[kFinal / 64];
+  const double pq = sum_partials(part_pq, n, sh);
+  if (threadIdx.x == 0) {
+    st->pq = pq;
+    const double a = st->rz / pq;
+    if (!(pq > 0.0) || !isfinite(a)) {
+      st->alpha = 0.0;
+      st->nonfinite = 1;
+      st->status = -4;
+      st->done = 1;
+    } else {
+      st->alpha = a;
+    }
+  }
+}
+
+// x += alpha p, r -= alpha q; partial r.r; Jacobi (dinv != null): z = dinv r
+// and partial r.z
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pcg_xr(int n, const PcgState* __restrict__ st,
+                                                   const T* __restrict__ p, const T* __restrict__ q,
+                                                   T* __restrict__ x, T* __restrict__ r,
+                                                   const T* __restrict__ dinv, T* __restrict__ z,
+                                                   double* __restrict__ part_rr,
+                                                   double* __restrict__ part_rz) {
+  if (st->done) return;
+  const T a = T(st->alpha);
+  double s = 0.0, t = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    x[i] += a * p[i];
+    const T ri = r[i] - a * q[i];
+    r[i] = ri;
+    s += double(ri) * double(ri);
+    if (dinv) {
+      const T zi = dinv[i] * ri;
+      z[i] = zi;
+      t += double(ri) * double(zi);
+    }
+  }
+  __shared__ double sh[kBlock / 64];
+  double v = block_sum<kBlock>(s, sh);
+  if (threadIdx.x == 0) part_rr[blockIdx.x] = v;
+  if (dinv) {
+    __syncthreads();
+    v = block_sum<kBlock>(t, sh);
+    if (threadIdx.x == 0) part_rz[blockIdx.x] = v;
+  }
+}
+
+// convergence test on r.r; with part_rz also the CG beta (Jacobi path)
+__global__ __launch_bounds__(kFinal) void k_pcg_check(PcgState* st, const double* part_rr, int nrr,
+                                                      const double* part_rz, int nrz) {
+  if (st->done) return;
+  __shared__ double sh[kFinal / 64];
+  const double rr = sum_partials(part_rr, nrr, sh);
+  double rz = 0.0;
+  if (part_rz) {
+    __syncthreads();
+    rz = sum_partials(part_rz, nrz, sh);
+  }
+  if (threadIdx.x == 0) {
+    st->rr = rr;
+    st->it += 1;
+    if (!isfinite(rr)) {
+      st->nonfinite = 1;
+      st->status = -4;
+      st->done = 1;
+    } else if (rr <= st->tol2 * st->rr0) {
+      st->done = 1;
+      st->status = 0;
+    } else if (st->it >= st->maxit) {
+      st->done = 1;
+      st->status = -5;
+    } else if (part_rz) {
+      st->beta = rz / st->rz;
+      st->rz = rz;
+    }
+  }
+}
+
+// preconditioned path: rz_new from the partials of the last V-cycle kernel
+__global__ __launch_bounds__(kFinal) void k_pcg_beta(PcgState* st, const double* part_rz, int n) {
+  if (st->done) return;
+  __shared__ double sh[kFinal / 64];
+  const double rz = sum_partials(part_rz, n, sh);
+  if (threadIdx.x == 0) {
+    st->beta = rz / st->rz;
+    st->rz = rz;
+  }
+}
+
+// p = z + beta p
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pcg_p(int n, const PcgState* __restrict__ st,
+                                                  const T* __restrict__ z, T* __restrict__ p) {
+  if (st->done) return;
+  const T b = T(st->beta);
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+    p[i] = z[i] + b * p[i];
+}
+
+// ------------------------------------------------------------ multigrid
+
+// Restriction of face residuals, full weighting: coarse face = (1/2^d) *
+// sum over the fine faces it covers, normal neighbours weighted 1/2
+// (transpose of the prolongation below divided by 2^d).
+template <typename T, int DIM, int C>
+__device__ __forceinline__ void restrict_face(const Grid& Gf, const Grid& Gc,
+                                              const T* __restrict__ rf, T* __restrict__ bc,
+                                              const PcgState* st, int idx, int k) {
+  const int e0 = Gc.ext[C][0], e1 = Gc.ext[C][1];
+  if (idx >= e0 * e1 || k >= Gc.ext[C][2]) return;
+  const int j = idx / e0, i = idx - j * e0;
+  const int P[3] = {i, j, k};
+  const int f = fidx<C>(Gc, i, j, k);
+  if (!unk<C>(Gc, P[C])) {
+    bc[f] = T(0);
+    return;
+  }
+  T acc = T(0);
+  const int nfC = Gf.n[C];
+#pragma unroll
+  for (int dn = -1; dn <= 1; ++dn) {
+    const int fn = 2 * P[C] + dn;
+    if (fn < 0 || fn > nfC) continue;
+    const T wn = dn == 0 ? T(1) : T(0.5);
+#pragma unroll
+    for (int t1 = 0; t1 < 2; ++t1)
+#pragma unroll
+      for (int t2 = 0; t2 < (DIM == 3 ? 2 : 1); ++t2) {
+        int Q[3];
+        Q[C] = fn;
+        const int A1 = (C + 1) % DIM;
+        const int A2 = (C + 2) % 3;
+        Q[A1] = 2 * P[A1] + t1;
+        if (DIM == 3) Q[A2] = 2 * P[A2] + t2;
+        else Q[2] = 0;
+        acc += wn * ldm<C>(Gf, rf, Q[0], Q[1], Q[2]);
+      }
+  }
+  bc[f] = acc * T(DIM == 3 ? 0.125 : 0.25);
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_restrict(Grid Gf, Grid Gc, const T* __restrict__ rf,
+                                                     T* __restrict__ bc, const PcgState* st) {
+  if (st && st->done) return;
+  const int c = blockIdx.z / Gc.nze;
+  const int k = blockIdx.z - c * Gc.nze;
+  const int idx = blockIdx.x * kBlock + threadIdx.x;
+  if (c == 0) restrict_face<T, DIM, 0>(Gf, Gc, rf, bc, st, idx, k);
+  else if (c == 1) restrict_face<T, DIM, 1>(Gf, Gc, rf, bc, st, idx, k);
+  else if (DIM == 3) restrict_face<T, DIM, 2>(Gf, Gc, rf, bc, st, idx, k);
+}
+
+// Prolongation + correction: fine faces coinciding with a coarse face take
+// its value, fine faces between two coarse faces the mean (linear in the
+// normal direction); constant across the two fine cells in tangential
+// directions.
+template <typename T, int DIM, int C>
+__device__ __forceinline__ void prolong_face(const Grid& Gf, const Grid& Gc,
+                                             const T* __restrict__ ec, T* __restrict__ xf, int idx,
+                                             int k) {
+  const int e0 = Gf.ext[C][0], e1 = Gf.ext[C][1];
+  if (idx >= e0 * e1 || k >= Gf.ext[C][2]) return;
+  const int j = idx / e0, i = idx - j * e0;
+  const int P[3] = {i, j, k};
+  if (!unk<C>(Gf, P[C])) return;
+  int Q[3] = {P[0] >> 1, P[1] >> 1, P[2] >> 1};
+  Q[C] = P[C] >> 1;
+  T v = ldm<C>(Gc, ec, Q[0], Q[1], Q[2]);
+  if (P[C] & 1) {
+    int R[3] = {Q[0], Q[1], Q[2]};
+    R[C] += 1;
+    v = T(0.5) * (v + ldm<C>(Gc, ec, R[0], R[1], R[2]));
+  }
+  xf[fidx<C>(Gf, i, j, k)] += v;
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_prolong_add(Grid Gf, Grid Gc, const T* __restrict__ ec,
+                                                        T* __restrict__ xf, const PcgState* st) {
+  if (st && st->done) return;
+  const int c = blockIdx.z / Gf.nze;
+  const int k = blockIdx.z - c * Gf.nze;
+  const int idx = blockIdx.x * kBlock + threadIdx.x;
+  if (c == 0) prolong_face<T, DIM, 0>(Gf, Gc, ec, xf, idx, k);
+  else if (c == 1) prolong_face<T, DIM, 1>(Gf, Gc, ec, xf, idx, k);
+  else if (DIM == 3) prolong_face<T, DIM, 2>(Gf, Gc, ec, xf, idx, k);
+}
+
+// x = Minv b on the coarsest grid: FP64 dense inverse (full-face layout,
+// zero rows/columns at non-unknown faces); one wave64 per row, b staged in LDS
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_coarse_gemv(int m, const double* __restrict__ Minv,
+                                                        const T* __restrict__ b, T* __restrict__ x,
+                                                        const PcgState* st) {
+  if (st && st->done) return;
+  extern __shared__ double sb[];
+  for (int i = threadIdx.x; i < m; i += kBlock) sb[i] = double(b[i]);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (row >= m) return;
+  const double* a = Minv + (size_t)row * m;
+  double s = 0.0;
+  for (int c = lane; c < m; c += 64) s += a[c] * sb[c];
+  s = wave_sum(s);
+  if (lane == 0) x[row] = T(s);
+}
+
+}  // namespace gkb

@@ -1,0 +1,199 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU FP64 oracle on the
+same seeded inputs.  Operators: element-wise; GKB with the Jacobi-PCG inner
+solve (the oracle's algorithm): relative 1e-10 in w and p at equal K."""
+import numpy as np
+import pytest
+
+import oracle
+import problems as P
+
+D, N = P.DIRICHLET, P.NATURAL
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _gk():
+    import paper_2001_10424_amd as gk
+    return gk
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _dev(x, dtype=None):
+    torch = _torch()
+    return torch.tensor(np.asarray(x), dtype=dtype or torch.float64, device="cuda")
+
+
+OP_GRIDS = [
+    ("channel2d", P.Grid(2, (64, 16, 1), 1 / 16, (D, N, D, D, D, D), -1)),
+    ("box2d_pin", P.Grid(2, (33, 20, 1), 1 / 20, (D,) * 6, 0)),
+    ("box3d_pin", P.Grid(3, (12, 10, 9), 0.1, (D,) * 6, 5)),
+    ("box3d_nat", P.Grid(3, (9, 8, 10), 0.125, (D, N, D, D, N, D), -1)),
+    ("ragged3d", P.Grid(3, (67, 5, 3), 0.2, (D,) * 6, 0)),
+]
+
+
+@pytest.mark.parametrize("name,grid", OP_GRIDS, ids=[n for n, _ in OP_GRIDS])
+@pytest.mark.parametrize("varmu", [False, True], ids=["mu1", "varmu"])
+def test_operators_fp64_match_oracle(name, grid, varmu):
+    _say("operators fp64", name, varmu)
+    gk = _gk()
+    mu = np.exp(np.random.default_rng(3).standard_normal(grid.n_cells)) if varmu else None
+    eta = 1e3
+    s = gk.Solver(grid, mu, eta, inner="jacobi")
+    assert (s.m_full, s.n_cells) == (grid.m_full, grid.n_cells)
+    assert (s.m_unknown, s.n_unknown) == (grid.m, grid.n_p)
+    x = P.random_vector(grid, 1)
+    x_full = np.random.default_rng(9).standard_normal(grid.m_full)  # garbage at Dirichlet faces
+    pc = np.random.default_rng(10).standard_normal(grid.n_cells)
+    refs = {
+        "W": oracle.apply_W(grid, x_full * grid.face_mask(), mu),
+        "M": oracle.apply_M(grid, x_full * grid.face_mask(), eta, mu),
+        "A": oracle.apply_A(grid, pc),
+        "AT": oracle.apply_AT(grid, x_full * grid.face_mask()),
+        "diag": oracle.diag_M(grid, eta, mu),
+    }
+    inputs = {"W": x_full, "M": x_full, "A": pc, "AT": x_full, "diag": None}
+    for op, ref in refs.items():
+        xin = None if inputs[op] is None else _dev(inputs[op])
+        y = s.apply(op, xin).cpu().numpy()
+        scale = np.abs(ref).max()
+        assert np.abs(y - ref).max() <= 1e-13 * scale, (op, np.abs(y - ref).max() / scale)
+    del x
+    s.close()
+
+
+@pytest.mark.parametrize("name,grid", OP_GRIDS[1:3], ids=[n for n, _ in OP_GRIDS[1:3]])
+def test_operators_fp32(name, grid):
+    _say("operators fp32", name)
+    torch = _torch()
+    gk = _gk()
+    mu = np.exp(np.random.default_rng(3).standard_normal(grid.n_cells))
+    s = gk.Solver(grid, mu, 1e3, inner="jacobi", precision="mixed")
+    x = P.random_vector(grid, 1).astype(np.float32)
+    for op, ref in [("M", oracle.apply_M(grid, x.astype(np.float64), 1e3, mu)),
+                    ("W", oracle.apply_W(grid, x.astype(np.float64), mu)),
+                    ("AT", oracle.apply_AT(grid, x.astype(np.float64)))]:
+        y = s.apply(op, _dev(x, torch.float32), precision="mixed").cpu().numpy()
+        scale = np.abs(ref).max()
+        assert np.abs(y - ref).max() <= 3e-6 * scale, (op, np.abs(y - ref).max() / scale)
+    s.close()
+
+
+def _gkb_pair(pr, tol, maxit, inner_tol=1e-13, delay=5, mu=None):
+    gk = _gk()
+    s = gk.Solver(pr.grid, mu, pr.eta, inner="jacobi", inner_tol=inner_tol, inner_maxit=500000,
+                  maxit=maxit)
+    w, p, info = s.solve(_dev(pr.g), _dev(pr.r), tol=tol, delay=delay)
+    ref = oracle.gkb_solve(pr.grid, pr.g, pr.r, pr.eta, mu=mu, tol=tol, delay=delay, maxit=maxit,
+                           inner_tol=inner_tol, inner_maxit=500000)
+    s.close()
+    return w.cpu().numpy(), p.cpu().numpy(), info, ref
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def test_poiseuille_gkb_parity_criterion():
+    """Poiseuille channel 64 x 16, eta = 1e2, tau = 1e-8, d = 5, Jacobi-PCG."""
+    _say("poiseuille criterion")
+    pr = P.poiseuille_problem(64, 16, 4.0, 1e2)
+    w, p, info, ref = _gkb_pair(pr, 1e-8, 300)
+    assert info["status"] == 0 and ref["status"] == 0
+    assert info["iterations"] == ref["K"]
+    assert _rel(w, ref["w"]) <= 1e-10 and _rel(p, ref["p"]) <= 1e-10
+    assert abs(info["error_estimate"] - ref["est"]) <= 1e-8 * ref["est"]
+    # zeta values below rounding level of zeta_1 carry no information
+    np.testing.assert_allclose(info["zeta"], ref["zeta"], rtol=1e-8,
+                               atol=1e-13 * abs(ref["zeta"][0]))
+    # physical check: discrete solution close to the exact Poiseuille flow
+    u = pr.extra["w_lift"] + w
+    assert np.sqrt(np.mean(((u - pr.extra["u_exact"]) * pr.grid.face_mask()) ** 2)) < 2e-3
+
+
+def test_poiseuille_gkb_parity_fixed_k():
+    _say("poiseuille fixed K")
+    pr = P.poiseuille_problem(64, 16, 4.0, 1e2)
+    w, p, info, ref = _gkb_pair(pr, 0.0, 7)
+    assert info["status"] == 1 and ref["status"] == 1 and info["iterations"] == 7
+    assert _rel(w, ref["w"]) <= 1e-10 and _rel(p, ref["p"]) <= 1e-10
+
+
+@pytest.mark.parametrize("dim,n,varmu,eta", [(2, 24, False, 10.0), (2, 16, True, 1e2),
+                                             (3, 8, False, 10.0), (3, 8, True, 1e2),
+                                             (2, 16, False, 0.0)])
+def test_stokes_gkb_parity(dim, n, varmu, eta):
+    _say("stokes parity", dim, n, varmu, eta)
+    pr = P.stokes_problem(dim, n, seed=1, eta=eta, lid=(dim == 3),
+                          mu_seed=(7 if varmu else None))
+    w, p, info, ref = _gkb_pair(pr, 1e-8, 400, mu=pr.mu)
+    assert info["status"] == ref["status"] == 0
+    assert info["iterations"] == ref["K"]
+    assert _rel(w, ref["w"]) <= 1e-10 and _rel(p, ref["p"]) <= 1e-10
+
+
+def test_zero_rhs_and_errors():
+    _say("zero rhs / errors")
+    torch = _torch()
+    gk = _gk()
+    g = P.Grid(2, (16, 16, 1), 1 / 16, (D,) * 6, 0)
+    s = gk.Solver(g, None, 10.0, inner="jacobi")
+    w, p, info = s.solve(torch.zeros(g.m_full, dtype=torch.float64, device="cuda"),
+                         torch.zeros(g.n_cells, dtype=torch.float64, device="cuda"))
+    assert info["iterations"] == 0 and float(w.abs().max()) == 0 and float(p.abs().max()) == 0
+    with pytest.raises(RuntimeError):
+        s.solve(torch.zeros(g.m_full, dtype=torch.float64, device="cuda"),
+                torch.zeros(g.n_cells, dtype=torch.float64, device="cuda"), delay=-1)
+    s.close()
+    with pytest.raises(RuntimeError):
+        gk.Solver(g, None, -1.0)
+    with pytest.raises(RuntimeError):
+        gk.Solver(P.Grid(2, (16, 16, 1), 0.0, (D,) * 6, 0), None, 1.0)
+    with pytest.raises(RuntimeError):  # every side natural: M singular for eta = 0
+        gk.Solver(P.Grid(2, (16, 16, 1), 1 / 16, (N,) * 6, -1), None, 0.0)
+
+
+def test_nan_input_reports_enan():
+    _say("nan input")
+    torch = _torch()
+    gk = _gk()
+    g = P.Grid(2, (16, 16, 1), 1 / 16, (D,) * 6, 0)
+    s = gk.Solver(g, None, 10.0, inner="jacobi")
+    gv = torch.tensor(P.random_vector(g, 1), device="cuda")
+    gv[40] = float("nan")
+    with pytest.raises(RuntimeError, match="non-finite"):
+        s.solve(gv, torch.zeros(g.n_cells, dtype=torch.float64, device="cuda"))
+    s.close()
+
+
+def test_inner_maxit_reports_einner():
+    _say("inner maxit")
+    torch = _torch()
+    gk = _gk()
+    g = P.Grid(2, (32, 32, 1), 1 / 32, (D,) * 6, 0)
+    s = gk.Solver(g, None, 1e3, inner="jacobi", inner_maxit=3, inner_tol=1e-12)
+    with pytest.raises(RuntimeError, match="inner"):
+        s.solve(torch.tensor(P.random_vector(g, 1), device="cuda"),
+                torch.zeros(g.n_cells, dtype=torch.float64, device="cuda"))
+    s.close()
+
+
+def test_deterministic_bitwise():
+    _say("determinism")
+    gk = _gk()
+    pr = P.stokes_problem(3, 16, seed=2, eta=1e2, lid=True)
+    s = gk.Solver(pr.grid, None, pr.eta, inner="mg", inner_tol=1e-10)
+    g, r = _dev(pr.g), _dev(pr.r)
+    w1, p1, i1 = s.solve(g, r, tol=1e-8)
+    w2, p2, i2 = s.solve(g, r, tol=1e-8)
+    assert bool((w1 == w2).all()) and bool((p1 == p2).all())
+    assert i1["inner_iterations"] == i2["inner_iterations"]
+    s.close()
