@@ -1,0 +1,203 @@
+"""Benchmark: wall seconds of one GKB solve of the 3D lid-driven Stokes
+problem on a 128^3 MAC grid (eta = 1e3) to an FP64 relative saddle residual
+of 1e-8, on one MI355X.
+
+A step is one complete gkb_solve (transformation, outer GKB recurrence, all
+inner multigrid-preconditioned solves, FP64 residual checks and
+defect-correction sweeps) on inputs already resident in HBM.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--mode mixed_mg]
+
+Prints one JSON line.  Besides the headline mode it times the FP64
+multigrid-GKB solve of the same problem (--compare), the dominant kernel's
+achieved bandwidth against the HBM roofline, and the CPU oracle on a bounded
+sample (cpu_baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
+
+MODES = {
+    # name: (precision, inner, gkb tol per sweep, inner tol)
+    "fp64_mg": ("fp64", "mg", 1e-9, 1e-10),
+    "mixed_mg": ("mixed", "mg", 1e-4, 1e-5),
+    "mixed_learned": ("mixed", "learned", 1e-4, 1e-5),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_solver(gk, pr, mode, weights=None):
+    prec, inner, _, itol = MODES[mode]
+    kw = dict(precision=prec, inner=inner, nu_pre=2, nu_post=2, inner_tol=itol,
+              inner_maxit=5000, maxit=200, refine_tol=1e-8, max_sweeps=12, check_every=8)
+    s = gk.Solver(pr.grid, pr.mu, pr.eta, **kw)
+    if inner == "learned":
+        s.attach_cnn(weights)
+    return s
+
+
+def time_mode(gk, torch, pr, mode, steps, warmup, g, r, weights=None):
+    t0 = time.perf_counter()
+    s = make_solver(gk, pr, mode, weights)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    tol = MODES[mode][2]
+    info = None
+    for _ in range(warmup):
+        w, p, info = s.solve(g, r, tol=tol, delay=5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        w, p, info = s.solve(g, r, tol=tol, delay=5)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    norms, _, _ = s.residual(g, r, w, p)
+    rel = norms[0] / norms[3]
+    return s, w, p, dict(seconds=dt, setup_s=setup_s, residual=rel, sweeps=info["sweeps"],
+                         outer_iterations=info["outer_iterations"],
+                         inner_iterations=info["inner_iterations"],
+                         inner_solves=info["inner_solves"], fallbacks=info["fallbacks"],
+                         mg_levels=info["mg_levels"])
+
+
+def cpu_baseline(pr):
+    """The CPU FP64 oracle (GKB + Jacobi-PCG) on a bounded sample: 20
+    Jacobi-PCG iterations on the full 128^3 problem (seconds per iteration),
+    and one complete oracle solve of the same problem at 16^3 (iteration
+    count); the iteration count is projected to 128^3 with the growth
+    exponent measured between 8^3 and 16^3 full oracle solves."""
+    import math
+
+    import oracle
+    import problems
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    oracle.lib()
+    t0 = time.perf_counter()
+    res = oracle.gkb_solve(pr.grid, pr.g, pr.r, pr.eta, mu=pr.mu, tol=1e-9, delay=5, maxit=1,
+                           inner_tol=1e-10, inner_maxit=20)
+    t_iter = (time.perf_counter() - t0) / 20.0
+    its = {}
+    t_small = {}
+    for n in (8, 16):
+        sp = problems.stokes_problem(3, n, seed=0, eta=pr.eta, lid=True)
+        t1 = time.perf_counter()
+        rs = oracle.gkb_solve(sp.grid, sp.g, sp.r, sp.eta, tol=1e-9, delay=5, maxit=200,
+                              inner_tol=1e-10, inner_maxit=10 ** 7)
+        t_small[n] = time.perf_counter() - t1
+        its[n] = rs["inner_total"]
+    expo = math.log(its[16] / its[8]) / math.log(2.0)
+    n_big = pr.grid.n[0]
+    its_big = its[16] * (n_big / 16.0) ** expo
+    projected = t_iter * its_big
+    del res
+    return {"value": projected, "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": (f"oracle FP64 GKB + Jacobi-PCG: {t_iter:.3f} s per inner iteration "
+                       f"measured over 20 iterations at {n_big}^3; full oracle solves at "
+                       f"8^3 / 16^3 took {its[8]} / {its[16]} inner iterations "
+                       f"({t_small[8]:.1f} s / {t_small[16]:.1f} s); projected "
+                       f"{its_big:.3g} iterations at {n_big}^3 (growth n^{expo:.2f})")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--mode", default="mixed_mg", choices=list(MODES))
+    ap.add_argument("--n", type=int, default=128, help="cells per axis of the 3D problem")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--weights", default=None, help="CNN weights for mixed_learned")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this solver build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import problems
+    import paper_2001_10424_amd as gk
+
+    torch.cuda.set_device(0)
+    pr = problems.stokes_problem(3, args.n, seed=args.seed, eta=1e3, lid=True)
+    g = torch.tensor(pr.g, device="cuda")
+    r = torch.tensor(pr.r, device="cuda")
+    log(f"[bench] workload stokes3d_{args.n}_lid m={pr.grid.m} n={pr.grid.n_p}")
+
+    s, w, p, main_res = time_mode(gk, torch, pr, args.mode, args.steps, args.warmup, g, r,
+                                  args.weights)
+    log(f"[bench] {args.mode}: {json.dumps(main_res)}")
+    compare = {args.mode: main_res}
+    if not args.no_compare:
+        for m in ("fp64_mg", "mixed_mg"):
+            if m == args.mode:
+                continue
+            s2, _, _, res2 = time_mode(gk, torch, pr, m, args.steps, args.warmup, g, r)
+            compare[m] = res2
+            s2.close()
+            log(f"[bench] {m}: {json.dumps(res2)}")
+
+    # dominant kernel: the finest-grid weighted-Jacobi sweep of the inner
+    # solve (reads x and b, writes y: 3 full-face vectors per launch)
+    elem = 4 if MODES[args.mode][0] == "mixed" else 8
+    reps = 50
+    ms = s.time_kernel("smooth", reps)
+    bytes_per_launch = 3 * s.m_full * elem
+    achieved = bytes_per_launch / (ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_face_op<kJacobi> finest grid", "avg_ms": round(ms, 5),
+                "bytes_per_launch": bytes_per_launch}
+    s.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(pr)
+        log(f"[bench] cpu_baseline {json.dumps(cpu)}")
+
+    out = {
+        "metric": "s to 1e-8 GKB solve, 3D 128^3 Stokes: FP64 MG vs FP32+learned PC; HBM GB/s",
+        "value": round(main_res["seconds"], 5),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_res["seconds"] * 1e3, 3),
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if MODES[args.mode][0] == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"stokes3d_{args.n}_lid: 3D Stokes, MAC {args.n}^3, mu=1, "
+                               f"lid u=1 on +z, 8-mode Fourier body force (seed {args.seed}), "
+                               f"eta=1e3, stop at FP64 relative saddle residual 1e-8",
+                   "mode": args.mode,
+                   "inner": "PCG with geometric MG V(2,2), weighted Jacobi, FP64 coarsest",
+                   "compare_seconds": {k: round(v["seconds"], 5) for k, v in compare.items()},
+                   "details": compare},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    del w, p, np
+
+
+if __name__ == "__main__":
+    main()

@@ -82,8 +82,10 @@ typedef struct {
 typedef struct {
   int precision;        /* GKB_FP64 or GKB_MIXED */
   int inner;            /* GKB_INNER_JACOBI / _MG / _LEARNED */
-  int mg_levels;        /* number of grid levels; 0 = coarsen while every n is
-                           even and > 8 */
+  int mg_levels;        /* number of grid levels; 0 = coarsen while the level
+                           has more than 2000 faces and every n is even and
+                           >= 4 (the coarsest level is solved with a dense
+                           FP64 inverse, at most 4096 faces) */
   int nu_pre, nu_post;  /* smoothing sweeps of the V-cycle */
   double inner_tol;     /* relative residual of each inner solve (tau_in) */
   int inner_maxit;
@@ -94,6 +96,9 @@ typedef struct {
   int max_sweeps;       /* cap on defect-correction sweeps */
   int check_every;      /* inner iterations between host convergence checks */
   int use_graphs;       /* capture inner iterations in HIP graphs (1) or not */
+  int stencil;          /* 0: LDS-tiled 3D stencil kernel where it applies (3D
+                           grids whose +x, +y, +z sides are DIRICHLET), generic
+                           face kernel elsewhere; 1: generic face kernel only */
   void *hip_stream;     /* hipStream_t; NULL = null stream */
   size_t max_workspace_bytes; /* 0 = unlimited; else setup fails with
                                  GKB_ENOMEM above this device footprint */
@@ -183,6 +188,21 @@ int gkb_inner_solve(gkb_ctx *c, const double *f, double *x, double tol,
    ||[g; r]||.  res_w / res_r may be NULL when only the norms are wanted. */
 int gkb_residual(gkb_ctx *c, const double *g, const double *r, const double *w,
                  const double *p, double *res_w, double *res_r, double *norms);
+
+/* ---- measurement ------------------------------------------------------ */
+
+#define GKB_KERNEL_SMOOTH 0  /* one weighted-Jacobi sweep y = x + omega D^-1 (b - M x)
+                                on the finest grid (reads x, b; writes y) */
+#define GKB_KERNEL_APPLY 1   /* y = M x with the fused x.y block partials */
+#define GKB_KERNEL_RESID 2   /* y = b - M x */
+
+/* Launch one finest-grid kernel of the inner solver `reps` times back to
+   back on the context's stream (working precision of the inner solve, on
+   the context's own PCG buffers) and return the average duration per launch
+   in milliseconds, measured with HIP events recorded on that stream.  Needs
+   inner = GKB_INNER_MG or GKB_INNER_LEARNED.  Does not change solver state
+   other than scratch vectors. */
+int gkb_time_kernel(gkb_ctx *c, int kernel, int reps, double *avg_ms);
 
 #ifdef __cplusplus
 }

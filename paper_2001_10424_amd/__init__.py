@@ -168,6 +168,14 @@ class Solver:
         _abi.check(rc, "gkb_inner_solve")
         return x, it.value
 
+    def time_kernel(self, kernel="smooth", reps=50):
+        """Average duration (ms) of one finest-grid inner kernel, timed with HIP
+        events on the library's stream (gkb_time_kernel)."""
+        ms = C.c_double(0.0)
+        _abi.check(_abi.lib().gkb_time_kernel(self._ctx, _abi.KERNELS[kernel], int(reps),
+                                              C.byref(ms)), "gkb_time_kernel")
+        return ms.value
+
     def residual(self, g, r, w, p, want_vectors=False):
         """FP64 saddle residual (gkb_residual): returns (norms, res_w, res_r);
         norms = (||res||, ||res_w||, ||res_r||, ||[g; r]||)."""

@@ -14,6 +14,7 @@ DIRICHLET, NATURAL = 0, 1
 FP64, MIXED = 0, 1
 INNER = {"jacobi": 0, "mg": 1, "learned": 2}
 OPS = {"W": 0, "A": 1, "AT": 2, "M": 3, "diag": 4}
+KERNELS = {"smooth": 0, "apply": 1, "resid": 2}
 
 # every symbol declared in include/gkb.h
 EXPORTS = [
@@ -36,6 +37,7 @@ class Options(C.Structure):
                 ("nu_pre", C.c_int), ("nu_post", C.c_int), ("inner_tol", C.c_double),
                 ("inner_maxit", C.c_int), ("maxit", C.c_int), ("refine_tol", C.c_double),
                 ("max_sweeps", C.c_int), ("check_every", C.c_int), ("use_graphs", C.c_int),
+                ("stencil", C.c_int),
                 ("hip_stream", C.c_void_p), ("max_workspace_bytes", C.c_size_t)]
 
 
@@ -86,6 +88,8 @@ def lib():
     L.gkb_inner_solve.restype = C.c_int
     L.gkb_residual.argtypes = [ctxp, P, P, P, P, P, P, P]
     L.gkb_residual.restype = C.c_int
+    L.gkb_time_kernel.argtypes = [ctxp, C.c_int, C.c_int, C.POINTER(C.c_double)]
+    L.gkb_time_kernel.restype = C.c_int
     _declare_cnn(L)
     _lib = L
     return L

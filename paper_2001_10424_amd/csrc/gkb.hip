@@ -27,6 +27,7 @@
 #include "../../include/gkb.h"
 #include "kernels.hpp"
 #include "learned.hpp"
+#include "tile3d.hpp"
 
 using namespace gkb;
 
@@ -55,10 +56,17 @@ int vec_blocks(int n) { return std::max(1, std::min((n + 1023) / 1024, 4096)); }
 
 struct FaceLaunch {
   dim3 grid;
-  int kz = 1, zchunks = 1, nparts = 0;
+  int kz = 1, zchunks = 1;
+  int nparts = 0;   // partials written by face_op's reduction modes
+  int gparts = 0;   // partials of kernels launched on the generic grid
+  bool tiled = false;  // LDS-tiled 3D kernel for the stencil modes
+  dim3 tgrid;
+  int tz = 8;
 };
 
-FaceLaunch face_launch(const Grid& g, int kz) {
+int g_tz = 0;  // z-planes per tiled block (0: default)
+
+FaceLaunch face_launch(const Grid& g, int kz, int stencil = 0) {
   FaceLaunch L;
   int maxplane = 0;
   for (int c = 0; c < g.dim; ++c) maxplane = std::max(maxplane, g.ext[c][0] * g.ext[c][1]);
@@ -66,6 +74,24 @@ FaceLaunch face_launch(const Grid& g, int kz) {
   L.zchunks = (g.nze + kz - 1) / kz;
   L.grid = dim3((maxplane + kBlock - 1) / kBlock, 1, g.dim * L.zchunks);
   L.nparts = L.grid.x * L.grid.z;
+  L.gparts = L.nparts;
+  // the tiled kernel covers the lower faces of every cell: the upper faces
+  // must be Dirichlet (zero) faces
+  const bool upper_dir = g.bc[1] == kDir && g.bc[3] == kDir && g.bc[5] == kDir;
+  if (stencil == 0 && g.dim == 3 && upper_dir) {
+    if (g_tz == 0) {
+      const char* e = std::getenv("GKB_TZ");
+      g_tz = e ? std::max(1, std::atoi(e)) : -1;
+    }
+    L.tiled = true;
+    const int tx = (g.n[0] + kTX - 1) / kTX, ty = (g.n[1] + kTY - 1) / kTY;
+    // z-planes per block: keep >= ~1024 blocks in flight (4 per CU); more
+    // planes per block amortise the z-halo but starve small grids
+    int tz = g_tz > 0 ? g_tz : std::max(1, std::min(4, tx * ty * g.n[2] / 1024));
+    L.tz = std::min(tz, g.n[2]);
+    L.tgrid = dim3(tx, ty, (g.n[2] + L.tz - 1) / L.tz);
+    L.nparts = L.tgrid.x * L.tgrid.y * L.tgrid.z;
+  }
   return L;
 }
 
@@ -94,6 +120,8 @@ struct Alloc {
     void* q = nullptr;
     if (hipMalloc(&q, std::max<size_t>(b, 256)) != hipSuccess) return GKB_ENOMEM;
     ptrs.push_back(q);
+    // zero-filled: faces that no kernel writes (Dirichlet faces) read as 0
+    if (hipMemset(q, 0, std::max<size_t>(b, 256)) != hipSuccess) return GKB_EHIP;
     bytes += b;
     *out = q;
     return GKB_OK;
@@ -182,6 +210,11 @@ void face_op(gkb_ctx* c, const Op<T>& op, const FaceLaunch& fl, const T* x, cons
   const bool vm = op.mu != nullptr;
   const int kz = fl.kz, zc = fl.zchunks;
   hipStream_t s = c->cs;
+  if (fl.tiled && MODE != kJacobi0 && MODE != kDiag) {
+    if (vm) k_tile3d<T, true, MODE><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st);
+    else k_tile3d<T, false, MODE><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st);
+    return;
+  }
   if (op.g.dim == 2) {
     if (vm) k_face_op<T, 2, true, MODE><<<fl.grid, kBlock, 0, s>>>(op, x, b, y, omega, kz, zc, partial, st);
     else k_face_op<T, 2, false, MODE><<<fl.grid, kBlock, 0, s>>>(op, x, b, y, omega, kz, zc, partial, st);
@@ -524,8 +557,8 @@ int residual_impl(gkb_ctx* c, const double* gv, const double* rv, const double* 
   }
   div_axpy<double>(c, G, w, rv, -1.0, 1.0, res_r ? res_r : c->t, c->part[2], c->part[3]);
   double rw = 0, ggw = 0, rrr = 0, rr2 = 0;
-  CK(host_sum(c, c->part[0], fl.nparts, &rw));
-  CK(host_sum(c, c->part[1], fl.nparts, &ggw));
+  CK(host_sum(c, c->part[0], fl.gparts, &rw));
+  CK(host_sum(c, c->part[1], fl.gparts, &ggw));
   CK(host_sum(c, c->part[2], cell_parts(G), &rrr));
   CK(host_sum(c, c->part[3], cell_parts(G), &rr2));
   norms[0] = std::sqrt(rw + rrr);
@@ -641,7 +674,7 @@ int build_inner(gkb_ctx* c, Inner<T>& in, const std::vector<Coef<T>>& coef) {
     lv.g = c->grids[l];
     lv.op = make_op<T>(lv.g, c->eta, coef[l], c->varmu);
     lv.omega = c->omega[l];
-    lv.fl = face_launch(lv.g, 4);
+    lv.fl = face_launch(lv.g, 4, c->opt.stencil);
     const int m = lv.g.m_full;
     if (l > 0) {
       CK(c->mem.arr(&lv.b, m));
@@ -687,10 +720,18 @@ int setup_impl(gkb_ctx* c, const gkb_grid* grid, const double* visc, double eta,
   if (L <= 0) {
     L = 1;
     int nn[3] = {n[0], n[1], n[2]};
+    // coarsen while the current level has more than 2000 faces and every
+    // axis halves to at least 2 cells (the coarsest level is solved densely)
     for (;;) {
       bool ok = true;
-      for (int a = 0; a < grid->dim; ++a) ok = ok && (nn[a] % 2 == 0) && (nn[a] > 8);
-      if (!ok || L >= kMaxLevels) break;
+      long mf = 0;
+      for (int cc = 0; cc < grid->dim; ++cc) {
+        long e = 1;
+        for (int a = 0; a < grid->dim; ++a) e *= nn[a] + (a == cc ? 1 : 0);
+        mf += e;
+      }
+      for (int a = 0; a < grid->dim; ++a) ok = ok && (nn[a] % 2 == 0) && (nn[a] >= 4);
+      if (!ok || mf <= 2000 || L >= kMaxLevels) break;
       for (int a = 0; a < grid->dim; ++a) nn[a] /= 2;
       ++L;
     }
@@ -749,11 +790,12 @@ int setup_impl(gkb_ctx* c, const gkb_grid* grid, const double* visc, double eta,
   }
   c->op64 = make_op<double>(c->g, eta, c->coef64[0], c->varmu);
   c->op32 = make_op<float>(c->g, eta, c->coef32[0], c->varmu);
-  c->fl0 = face_launch(c->g, 4);
+  c->fl0 = face_launch(c->g, 4, c->opt.stencil);
   // partial buffers: the largest reduction launch over all levels
   int maxp = 0;
   for (int l = 0; l < L; ++l) {
-    maxp = std::max(maxp, face_launch(c->grids[l], 4).nparts);
+    maxp = std::max(maxp, face_launch(c->grids[l], 4, c->opt.stencil).nparts);
+    maxp = std::max(maxp, face_launch(c->grids[l], 4, 1).nparts);
     maxp = std::max(maxp, cell_parts(c->grids[l]));
     maxp = std::max(maxp, vec_blocks(c->grids[l].m_full));
   }
@@ -771,7 +813,7 @@ int setup_impl(gkb_ctx* c, const gkb_grid* grid, const double* visc, double eta,
   for (int l = 0; l < L - (L > 1 ? 1 : 0); ++l) {
     const Grid& g = c->grids[l];
     Op<double> op = make_op<double>(g, eta, c->coef64[l], c->varmu);
-    FaceLaunch fl = face_launch(g, 4);
+    FaceLaunch fl = face_launch(g, 4, c->opt.stencil);
     double *xa, *ya;
     CK(c->mem.arr(&xa, g.m_full));
     CK(c->mem.arr(&ya, g.m_full));
@@ -864,6 +906,7 @@ int validate(const gkb_grid* g, double eta, const gkb_options* o) {
   if (o->inner < 0 || o->inner > 2) return GKB_EINVAL;
   if (o->nu_pre < 0 || o->nu_post < 0 || o->nu_pre + o->nu_post < 1) return GKB_EINVAL;
   if (o->inner_maxit < 1 || o->maxit < 1 || o->max_sweeps < 1) return GKB_EINVAL;
+  if (o->check_every < 1 || o->stencil < 0 || o->stencil > 1) return GKB_EINVAL;
   return GKB_OK;
 }
 
@@ -887,6 +930,7 @@ void gkb_default_options(gkb_options* o) {
   o->max_sweeps = 10;
   o->check_every = 8;
   o->use_graphs = 1;
+  o->stencil = 0;
   o->hip_stream = nullptr;
   o->max_workspace_bytes = 0;
 }
@@ -1108,4 +1152,41 @@ int gkb_residual(gkb_ctx* c, const double* g, const double* r, const double* w, 
 }
 
 }  // extern "C"
+
+namespace {
+template <typename T>
+int time_kernel_impl(gkb_ctx* c, Inner<T>& in, int kernel, int reps, double* avg_ms) {
+  if (!in.ready || reps < 1) return GKB_EINVAL;
+  Level<T>& L = in.lv[0];
+  hipEvent_t e0, e1;
+  HIPCK(hipEventCreate(&e0));
+  HIPCK(hipEventCreate(&e1));
+  auto one = [&]() {
+    if (kernel == GKB_KERNEL_SMOOTH)
+      face_op<T, kJacobi>(c, L.op, L.fl, in.z, in.r, L.t, T(L.omega), nullptr, nullptr);
+    else if (kernel == GKB_KERNEL_APPLY)
+      face_op<T, kApplyDot>(c, L.op, L.fl, in.p, nullptr, in.q, T(0), c->part[0], nullptr);
+    else
+      face_op<T, kResid>(c, L.op, L.fl, in.z, in.r, L.rb, T(0), nullptr, nullptr);
+  };
+  one();  // warm-up launch
+  HIPCK(hipEventRecord(e0, c->cs));
+  for (int i = 0; i < reps; ++i) one();
+  HIPCK(hipEventRecord(e1, c->cs));
+  HIPCK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCK(hipEventElapsedTime(&ms, e0, e1));
+  *avg_ms = double(ms) / reps;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return GKB_OK;
+}
+}  // namespace
+
+extern "C" int gkb_time_kernel(gkb_ctx* c, int kernel, int reps, double* avg_ms) {
+  if (!c || !avg_ms || kernel < 0 || kernel > 2 || c->opt.inner == GKB_INNER_JACOBI) return GKB_EINVAL;
+  if (c->opt.precision == GKB_MIXED) return time_kernel_impl<float>(c, c->in32, kernel, reps, avg_ms);
+  return time_kernel_impl<double>(c, c->in64, kernel, reps, avg_ms);
+}
+
 #include "learned_impl.hpp"

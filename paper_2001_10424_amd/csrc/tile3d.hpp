@@ -1,0 +1,301 @@
+// LDS-tiled 3D MAC stencil for M = W + eta A A^T (and the Jacobi / residual
+// variants built on it) on grids whose +x, +y, +z sides are DIRICHLET.
+//
+// A block of 256 threads (4 wave64) owns a tile of 64 x 8 cells in x-y and
+// marches through `tz` consecutive z-planes.  Each thread owns one x
+// position and two y rows and produces the three "lower" faces u(i,j,k),
+// v(i,j,k), w(i,j,k) of its cells; the upper boundary faces (i = nx, ...)
+// are Dirichlet faces and are written as 0 by the last row / column / plane.
+//
+// Per z-plane the block stages the face values of the plane k+1 of u, v, w
+// for the tile plus a one-cell halo in a two-slot LDS ring (plane k is
+// already there), computes the cell divergence of plane k for the tile plus
+// its lower halo row/column once into LDS (it feeds the grad-div term of up
+// to six faces), and keeps the plane k-1 values of its own faces and the
+// divergence of its cell below in registers.  Global traffic per plane is one
+// pass over the tile (+ halo, mostly L2 hits) of x, plus b and y for the
+// faces the block owns.
+#pragma once
+#include "kernels.hpp"
+
+namespace gkb {
+
+constexpr int kTX = 64;          // tile width (cells) = threads in x
+constexpr int kTYT = 4;          // threads in y
+constexpr int kRPT = 2;          // rows per thread
+constexpr int kTY = kTYT * kRPT; // tile height (cells)
+constexpr int kLX = kTX + 2;
+constexpr int kLY = kTY + 2;
+
+template <typename T>
+struct TileLds {
+  T u[2][kLY][kLX];
+  T v[2][kLY][kLX];
+  T w[2][kLY][kLX];
+  T cd[kTY + 1][kTX + 1];
+};
+
+// one axis of the viscous stencil; lo_in / hi_in: neighbour inside the array,
+// lo_wall / hi_wall: neighbour across a DIRICHLET wall (mirror ghost)
+template <typename T>
+__device__ __forceinline__ void visc_axis(T xf, T vlo, T vhi, bool lo_in, bool hi_in, bool lo_wall,
+                                          bool hi_wall, T klo, T khi, T wgt, T& acc, T& d) {
+  if (lo_in) {
+    acc += wgt * klo * (xf - vlo);
+    d += wgt * klo;
+  } else if (lo_wall) {
+    acc += T(2) * wgt * klo * xf;
+    d += T(2) * wgt * klo;
+  }
+  if (hi_in) {
+    acc += wgt * khi * (xf - vhi);
+    d += wgt * khi;
+  } else if (hi_wall) {
+    acc += T(2) * wgt * khi * xf;
+    d += T(2) * wgt * khi;
+  }
+}
+
+template <int MODE>
+constexpr bool reads_b() {
+  return MODE == kJacobi || MODE == kJacobiDot || MODE == kResid || MODE == kResidDot;
+}
+
+// bf: b at the face (prefetched by the caller when the mode reads b)
+template <typename T, int MODE>
+__device__ __forceinline__ double tile_finish(int f, T mx, T d, T xf, T bf, T* __restrict__ y,
+                                              T omega) {
+  double part = 0.0;
+  T out;
+  if (MODE == kApply || MODE == kApplyDot) {
+    out = mx;
+    if (MODE == kApplyDot) part = double(xf) * double(out);
+  } else if (MODE == kJacobi || MODE == kJacobiDot) {
+    out = xf + omega * (bf - mx) / d;
+    if (MODE == kJacobiDot) part = double(bf) * double(out);
+  } else if (MODE == kResid || MODE == kResidDot) {
+    out = bf - mx;
+    if (MODE == kResidDot) part = double(out) * double(out);
+  } else {  // kDinvM
+    out = mx / d;
+    part = double(out) * double(out);
+  }
+  y[f] = out;
+  return part;
+}
+
+template <typename T, bool VARMU, int MODE>
+__global__ __launch_bounds__(256) void k_tile3d(Op<T> op, const T* __restrict__ x,
+                                                const T* __restrict__ b, T* __restrict__ y,
+                                                T omega, int tz, double* __restrict__ partial,
+                                                const PcgState* __restrict__ st) {
+  if (st && st->done) return;
+  __shared__ TileLds<T> S;
+  const Grid& G = op.g;
+  const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
+  // XCD-aware block order: consecutive logical tiles on the same XCD
+  const int nb = gridDim.x * gridDim.y * gridDim.z;
+  int lin = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  if ((nb & 7) == 0) lin = (lin & 7) * (nb >> 3) + (lin >> 3);
+  const int bx = lin % gridDim.x;
+  const int rest = lin / gridDim.x;
+  const int by = rest % gridDim.y, bz = rest / gridDim.y;
+  const int i0 = bx * kTX, j0 = by * kTY, k0 = bz * tz;
+  const int k1 = min(k0 + tz, nz);
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const bool unk_u0 = G.bc[0] == kNat, unk_v0 = G.bc[2] == kNat, unk_w0 = G.bc[4] == kNat;
+
+  auto load_plane = [&](int k, int s) {
+    for (int e = threadIdx.x; e < kLX * kLY; e += 256) {
+      const int jj = e / kLX, ii = e - jj * kLX;
+      const int i = i0 - 1 + ii, j = j0 - 1 + jj;
+      T uu = T(0), vv = T(0), ww = T(0);
+      const bool jin = j >= 0 && j < ny, iin = i >= 0 && i < nx;
+      if (k >= 0 && k < nz) {
+        if (jin && i >= 0 && i < nx && (i > 0 || unk_u0)) uu = x[fidx<0>(G, i, j, k)];
+        if (iin && j >= 0 && j < ny && (j > 0 || unk_v0)) vv = x[fidx<1>(G, i, j, k)];
+      }
+      if (k >= 0 && k < nz && iin && jin && (k > 0 || unk_w0)) ww = x[fidx<2>(G, i, j, k)];
+      S.u[s][jj][ii] = uu;
+      S.v[s][jj][ii] = vv;
+      S.w[s][jj][ii] = ww;
+    }
+  };
+  auto cell_ok = [&](int i, int j, int k) {
+    return i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz && cidx(G, i, j, k) != G.pin;
+  };
+
+  T up[kRPT], vp[kRPT], wp[kRPT], cdp[kRPT];
+  load_plane(k0 - 1, 1);
+  load_plane(k0, 0);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRPT; ++r) {
+    const int jj = ty + r * kTYT + 1, ii = tx + 1;
+    const int i = i0 + tx, j = j0 + ty + r * kTYT;
+    up[r] = S.u[1][jj][ii];
+    vp[r] = S.v[1][jj][ii];
+    wp[r] = S.w[1][jj][ii];
+    cdp[r] = cell_ok(i, j, k0 - 1)
+                 ? (S.u[1][jj][ii] - S.u[1][jj][ii + 1] + S.v[1][jj][ii] - S.v[1][jj + 1][ii] +
+                    S.w[1][jj][ii] - S.w[0][jj][ii])
+                 : T(0);
+  }
+  __syncthreads();
+
+  const T eta = op.eta, ih2 = op.ih2;
+  double part = 0.0;
+  for (int k = k0; k < k1; ++k) {
+    const int s = (k - k0) & 1, s1 = s ^ 1;
+    // b of this thread's faces, issued together with the plane loads
+    T bu[kRPT], bv[kRPT], bw[kRPT];
+#pragma unroll
+    for (int r = 0; r < kRPT; ++r) {
+      bu[r] = bv[r] = bw[r] = T(0);
+      const int i = i0 + tx, j = j0 + ty + r * kTYT;
+      if (reads_b<MODE>() && i < nx && j < ny) {
+        bu[r] = b[fidx<0>(G, i, j, k)];
+        bv[r] = b[fidx<1>(G, i, j, k)];
+        bw[r] = b[fidx<2>(G, i, j, k)];
+      }
+    }
+    load_plane(k + 1, s1);
+    __syncthreads();
+    // divergence sums of plane k for cells (i0-1 .. i0+63) x (j0-1 .. j0+7)
+    for (int e = threadIdx.x; e < (kTX + 1) * (kTY + 1); e += 256) {
+      const int cj = e / (kTX + 1), ci = e - cj * (kTX + 1);
+      const int i = i0 - 1 + ci, j = j0 - 1 + cj;
+      T v = T(0);
+      if (cell_ok(i, j, k))
+        v = S.u[s][cj][ci] - S.u[s][cj][ci + 1] + S.v[s][cj][ci] - S.v[s][cj + 1][ci] +
+            S.w[s][cj][ci] - S.w[s1][cj][ci];
+      S.cd[cj][ci] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRPT; ++r) {
+      const int jj = ty + r * kTYT + 1, ii = tx + 1;
+      const int i = i0 + tx, j = j0 + ty + r * kTYT;
+      if (i < nx && j < ny) {
+        const T cR = S.cd[jj][ii];
+        const bool okR = cell_ok(i, j, k);
+        // ---- u-face (i, j, k): normal x
+        {
+          const int f = fidx<0>(G, i, j, k);
+          if (i > 0 || unk_u0) {
+            const T xf = S.u[s][jj][ii];
+            T acc = T(0), d = T(0);
+            T kn0 = T(1), kn1 = T(1), ky0 = T(1), ky1 = T(1), kz0 = T(1), kz1 = T(1);
+            if (VARMU) {
+              if (i > 0) kn0 = op.mu[cidx(G, i - 1, j, k)];
+              kn1 = op.mu[cidx(G, i, j, k)];
+              ky0 = edge_mu<2>(op, i, j, k);
+              ky1 = edge_mu<2>(op, i, j + 1, k);
+              kz0 = edge_mu<1>(op, i, j, k);
+              kz1 = edge_mu<1>(op, i, j, k + 1);
+            }
+            visc_axis<T>(xf, S.u[s][jj][ii - 1], S.u[s][jj][ii + 1], i > 0, true, false, false,
+                         kn0, kn1, T(1), acc, d);
+            const T wgt = (i == 0) ? T(0.5) : T(1);
+            visc_axis<T>(xf, S.u[s][jj - 1][ii], S.u[s][jj + 1][ii], j > 0, j < ny - 1,
+                         G.bc[2] == kDir, G.bc[3] == kDir, ky0, ky1, wgt, acc, d);
+            visc_axis<T>(xf, up[r], S.u[s1][jj][ii], k > 0, k < nz - 1, G.bc[4] == kDir,
+                         G.bc[5] == kDir, kz0, kz1, wgt, acc, d);
+            if (eta != T(0)) {
+              const T cL = S.cd[jj][ii - 1];
+              const int cnt = int(okR) + int(cell_ok(i - 1, j, k));
+              acc += eta * (cR - cL);
+              d += eta * T(cnt);
+            }
+            part += tile_finish<T, MODE>(f, acc * ih2, d * ih2, xf, bu[r], y, omega);
+          } else {
+            y[f] = T(0);
+          }
+        }
+        // ---- v-face (i, j, k): normal y
+        {
+          const int f = fidx<1>(G, i, j, k);
+          if (j > 0 || unk_v0) {
+            const T xf = S.v[s][jj][ii];
+            T acc = T(0), d = T(0);
+            T kn0 = T(1), kn1 = T(1), kx0 = T(1), kx1 = T(1), kz0 = T(1), kz1 = T(1);
+            if (VARMU) {
+              if (j > 0) kn0 = op.mu[cidx(G, i, j - 1, k)];
+              kn1 = op.mu[cidx(G, i, j, k)];
+              kx0 = edge_mu<2>(op, i, j, k);
+              kx1 = edge_mu<2>(op, i + 1, j, k);
+              kz0 = edge_mu<0>(op, i, j, k);
+              kz1 = edge_mu<0>(op, i, j, k + 1);
+            }
+            visc_axis<T>(xf, S.v[s][jj - 1][ii], S.v[s][jj + 1][ii], j > 0, true, false, false,
+                         kn0, kn1, T(1), acc, d);
+            const T wgt = (j == 0) ? T(0.5) : T(1);
+            visc_axis<T>(xf, S.v[s][jj][ii - 1], S.v[s][jj][ii + 1], i > 0, i < nx - 1,
+                         G.bc[0] == kDir, G.bc[1] == kDir, kx0, kx1, wgt, acc, d);
+            visc_axis<T>(xf, vp[r], S.v[s1][jj][ii], k > 0, k < nz - 1, G.bc[4] == kDir,
+                         G.bc[5] == kDir, kz0, kz1, wgt, acc, d);
+            if (eta != T(0)) {
+              const T cL = S.cd[jj - 1][ii];
+              const int cnt = int(okR) + int(cell_ok(i, j - 1, k));
+              acc += eta * (cR - cL);
+              d += eta * T(cnt);
+            }
+            part += tile_finish<T, MODE>(f, acc * ih2, d * ih2, xf, bv[r], y, omega);
+          } else {
+            y[f] = T(0);
+          }
+        }
+        // ---- w-face (i, j, k): normal z
+        {
+          const int f = fidx<2>(G, i, j, k);
+          if (k > 0 || unk_w0) {
+            const T xf = S.w[s][jj][ii];
+            T acc = T(0), d = T(0);
+            T kn0 = T(1), kn1 = T(1), kx0 = T(1), kx1 = T(1), ky0 = T(1), ky1 = T(1);
+            if (VARMU) {
+              if (k > 0) kn0 = op.mu[cidx(G, i, j, k - 1)];
+              kn1 = op.mu[cidx(G, i, j, k)];
+              kx0 = edge_mu<1>(op, i, j, k);
+              kx1 = edge_mu<1>(op, i + 1, j, k);
+              ky0 = edge_mu<0>(op, i, j, k);
+              ky1 = edge_mu<0>(op, i, j + 1, k);
+            }
+            visc_axis<T>(xf, wp[r], S.w[s1][jj][ii], k > 0, true, false, false, kn0, kn1, T(1),
+                         acc, d);
+            const T wgt = (k == 0) ? T(0.5) : T(1);
+            visc_axis<T>(xf, S.w[s][jj][ii - 1], S.w[s][jj][ii + 1], i > 0, i < nx - 1,
+                         G.bc[0] == kDir, G.bc[1] == kDir, kx0, kx1, wgt, acc, d);
+            visc_axis<T>(xf, S.w[s][jj - 1][ii], S.w[s][jj + 1][ii], j > 0, j < ny - 1,
+                         G.bc[2] == kDir, G.bc[3] == kDir, ky0, ky1, wgt, acc, d);
+            if (eta != T(0)) {
+              const int cnt = int(okR) + int(cell_ok(i, j, k - 1));
+              acc += eta * (cR - cdp[r]);
+              d += eta * T(cnt);
+            }
+            part += tile_finish<T, MODE>(f, acc * ih2, d * ih2, xf, bw[r], y, omega);
+          } else {
+            y[f] = T(0);
+          }
+        }
+        // upper boundary faces are Dirichlet faces: keep them zero
+        if (i == nx - 1) y[fidx<0>(G, nx, j, k)] = T(0);
+        if (j == ny - 1) y[fidx<1>(G, i, ny, k)] = T(0);
+        if (k == nz - 1) y[fidx<2>(G, i, j, nz)] = T(0);
+        up[r] = S.u[s][jj][ii];
+        vp[r] = S.v[s][jj][ii];
+        wp[r] = S.w[s][jj][ii];
+        cdp[r] = cR;
+      }
+    }
+    __syncthreads();
+  }
+  constexpr bool kRed = MODE == kApplyDot || MODE == kJacobiDot || MODE == kDinvM || MODE == kResidDot;
+  if (kRed) {
+    __shared__ double sh[256 / 64];
+    double t = block_sum<256>(part, sh);
+    if (threadIdx.x == 0)
+      partial[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = t;
+  }
+}
+
+}  // namespace gkb

@@ -1,0 +1,172 @@
+"""Multigrid-preconditioned inner solves and mixed precision on the GPU:
+V-cycle symmetry / positivity, agreement of the LDS-tiled and generic stencil
+kernels, MG-PCG against the oracle's Jacobi-PCG solution, MG-GKB parity with
+the oracle at tight tolerances, and the FP64 saddle residual of mixed-precision
+solves recomputed by the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import problems as P
+
+D, N = P.DIRICHLET, P.NATURAL
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _dev(x, dtype=None):
+    import torch
+    return torch.tensor(np.asarray(x), dtype=dtype or torch.float64, device="cuda")
+
+
+def _gk():
+    import paper_2001_10424_amd as gk
+    return gk
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+MG_CASES = [
+    ("3d32_eta1e3", P.Grid(3, (32, 32, 32), 1 / 32, (D,) * 6, 0), 1e3, False),
+    ("3d_ragged_varmu", P.Grid(3, (48, 16, 24), 1 / 16, (D,) * 6, 0), 1e2, True),
+    ("2d64", P.Grid(2, (64, 64, 1), 1 / 64, (D,) * 6, 0), 1e3, False),
+    ("2d_channel", P.Grid(2, (64, 16, 1), 1 / 16, (D, N, D, D, D, D), -1), 1e2, False),
+    ("3d_natural", P.Grid(3, (16, 16, 16), 1 / 16, (D, N, D, D, D, D), -1), 10.0, False),
+]
+
+
+def _mu(g, on):
+    return np.exp(np.random.default_rng(5).standard_normal(g.n_cells)) if on else None
+
+
+@pytest.mark.parametrize("name,grid,eta,varmu", MG_CASES, ids=[c[0] for c in MG_CASES])
+def test_vcycle_symmetric_positive(name, grid, eta, varmu):
+    _say("vcycle sym", name)
+    gk = _gk()
+    s = gk.Solver(grid, _mu(grid, varmu), eta, inner="mg")
+    x = _dev(P.random_vector(grid, 1))
+    y = _dev(P.random_vector(grid, 2))
+    Vx = s.precondition(x)
+    Vy = s.precondition(y)
+    a = float((x * Vy).sum())
+    b = float((y * Vx).sum())
+    assert abs(a - b) <= 1e-11 * max(abs(a), abs(b)), (a, b)
+    assert float((x * Vx).sum()) > 0 and float((y * Vy).sum()) > 0
+    # non-unknown faces stay zero
+    mask = _dev(grid.face_mask())
+    assert float((Vx * (1 - mask)).abs().max()) == 0.0
+    s.close()
+
+
+@pytest.mark.parametrize("name,grid,eta,varmu", MG_CASES[:2], ids=[c[0] for c in MG_CASES[:2]])
+def test_tiled_matches_generic(name, grid, eta, varmu):
+    """The LDS-tiled 3D kernel and the generic face kernel compute the same
+    operator, V-cycle (every smoother / residual mode) and inner solve."""
+    _say("tiled vs generic", name)
+    gk = _gk()
+    mu = _mu(grid, varmu)
+    s0 = gk.Solver(grid, mu, eta, inner="mg", stencil=0)
+    s1 = gk.Solver(grid, mu, eta, inner="mg", stencil=1)
+    x = _dev(np.random.default_rng(3).standard_normal(grid.m_full))
+    for op in ("M", "W"):
+        a, b = s0.apply(op, x).cpu().numpy(), s1.apply(op, x).cpu().numpy()
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+    r = _dev(P.random_vector(grid, 4))
+    a, b = s0.precondition(r).cpu().numpy(), s1.precondition(r).cpu().numpy()
+    assert _rel(a, b) <= 1e-12
+    # rounding-order differences can move the stopping iteration of a slowly
+    # converging CG by a few steps; both solutions meet the tolerance
+    xa, ia = s0.inner_solve(r, 1e-9)
+    xb, ib = s1.inner_solve(r, 1e-9)
+    assert abs(ia - ib) <= 2 + 0.03 * ib
+    assert _rel(xa.cpu().numpy(), xb.cpu().numpy()) <= 1e-6
+    s0.close()
+    s1.close()
+
+
+def test_vcycle_laplacian_convergence_factor():
+    """eta = 0 (M = W, the vector Laplacian): MG-PCG converges in few
+    iterations, independent of the grid size (textbook multigrid)."""
+    _say("laplacian mg")
+    gk = _gk()
+    its = []
+    for n in (16, 32, 64):
+        g = P.Grid(3, (n, n, n), 1 / n, (D,) * 6, 0)
+        s = gk.Solver(g, None, 0.0, inner="mg")
+        f = _dev(P.random_vector(g, 3))
+        _, it = s.inner_solve(f, 1e-8)
+        its.append(it)
+        s.close()
+    assert max(its) <= 20 and its[-1] <= its[0] + 4, its
+
+
+@pytest.mark.parametrize("name,grid,eta,varmu", MG_CASES, ids=[c[0] for c in MG_CASES])
+def test_mg_pcg_solution_matches_oracle(name, grid, eta, varmu):
+    _say("mg-pcg vs oracle", name)
+    gk = _gk()
+    mu = _mu(grid, varmu)
+    s = gk.Solver(grid, mu, eta, inner="mg", inner_maxit=20000)
+    f = P.random_vector(grid, 6)
+    x, it = s.inner_solve(_dev(f), 1e-12)
+    ref, st, _ = oracle.pcg(grid, f, eta, mu, tol=1e-13, maxit=10 ** 6)
+    assert st == 0
+    assert _rel(x.cpu().numpy(), ref) <= 1e-7
+    # residual of the GPU solution in FP64 by the oracle's operator
+    res = f - oracle.apply_M(grid, x.cpu().numpy(), eta, mu)
+    assert np.linalg.norm(res) <= 1e-11 * np.linalg.norm(f)
+    s.close()
+
+
+@pytest.mark.parametrize("dim,n,varmu", [(3, 16, False), (2, 32, True)])
+def test_mg_gkb_matches_oracle(dim, n, varmu):
+    """GKB with the MG-PCG inner solve against the oracle (Jacobi-PCG inner):
+    both inner solves converged to 1e-13, so the GKB iterates agree."""
+    _say("mg-gkb vs oracle", dim, n, varmu)
+    gk = _gk()
+    pr = P.stokes_problem(dim, n, seed=3, eta=1e2, lid=True, mu_seed=(7 if varmu else None))
+    s = gk.Solver(pr.grid, pr.mu, pr.eta, inner="mg", inner_tol=1e-13, inner_maxit=50000)
+    w, p, info = s.solve(_dev(pr.g), _dev(pr.r), tol=1e-9, delay=5)
+    ref = oracle.gkb_solve(pr.grid, pr.g, pr.r, pr.eta, mu=pr.mu, tol=1e-9, delay=5, maxit=300,
+                           inner_tol=1e-13, inner_maxit=10 ** 6)
+    assert info["iterations"] == ref["K"]
+    assert _rel(w.cpu().numpy(), ref["w"]) <= 1e-8
+    assert _rel(p.cpu().numpy(), ref["p"]) <= 1e-8
+    s.close()
+
+
+@pytest.mark.parametrize("dim,n,varmu,eta", [(3, 32, False, 1e3), (2, 64, True, 1e3),
+                                             (3, 16, True, 1e2)])
+def test_mixed_precision_residual(dim, n, varmu, eta):
+    """FP32 inner MG-PCG inside FP64 GKB sweeps with FP64 defect correction:
+    the FP64 saddle residual, recomputed by the oracle, is <= 1e-8; the
+    difference to the oracle's FP64 solution is reported against it."""
+    _say("mixed", dim, n, varmu, eta)
+    gk = _gk()
+    pr = P.stokes_problem(dim, n, seed=4, eta=eta, lid=(dim == 3), mu_seed=(8 if varmu else None))
+    s = gk.Solver(pr.grid, pr.mu, pr.eta, precision="mixed", inner="mg", inner_tol=1e-5,
+                  refine_tol=1e-8, max_sweeps=12, maxit=200)
+    w, p, info = s.solve(_dev(pr.g), _dev(pr.r), tol=1e-4, delay=5)
+    wn, pn = w.cpu().numpy(), p.cpu().numpy()
+    _, _, nr = oracle.saddle_residual(pr.grid, pr.g, pr.r, wn, pn, mu=pr.mu)
+    assert nr[0] <= 1e-8 * nr[3], nr[0] / nr[3]
+    assert info["residual"] <= 1e-8 and info["sweeps"] >= 2
+    # library residual agrees with the oracle's
+    assert abs(info["residual"] - nr[0] / nr[3]) <= 1e-6 * nr[0] / nr[3] + 1e-15
+    s.close()
+
+
+def test_fp64_mg_refinement_residual():
+    _say("fp64 refine")
+    gk = _gk()
+    pr = P.stokes_problem(3, 32, seed=0, eta=1e3, lid=True)
+    s = gk.Solver(pr.grid, None, pr.eta, inner="mg", inner_tol=1e-10, refine_tol=1e-8)
+    w, p, info = s.solve(_dev(pr.g), _dev(pr.r), tol=1e-9, delay=5)
+    _, _, nr = oracle.saddle_residual(pr.grid, pr.g, pr.r, w.cpu().numpy(), p.cpu().numpy())
+    assert nr[0] <= 1e-8 * nr[3]
+    s.close()
