@@ -14,7 +14,7 @@ import ctypes as C
 
 from . import _abi
 
-__all__ = ["Solver", "library"]
+__all__ = ["Solver", "library", "CNN"]
 
 
 def library():
@@ -176,6 +176,15 @@ class Solver:
                                               C.byref(ms)), "gkb_time_kernel")
         return ms.value
 
+    def attach_cnn(self, net):
+        """Use a CNN (paper_2001_10424_amd.CNN, or a checkpoint path) in the
+        learned inner solves."""
+        from .cnn import CNN, attach
+        if isinstance(net, str):
+            net = CNN.load(net)
+        attach(self, net)
+        return net
+
     def residual(self, g, r, w, p, want_vectors=False):
         """FP64 saddle residual (gkb_residual): returns (norms, res_w, res_r);
         norms = (||res||, ||res_w||, ||res_r||, ||[g; r]||)."""
@@ -185,3 +194,6 @@ class Solver:
         _abi.check(_abi.lib().gkb_residual(self._ctx, _ptr(g), _ptr(r), _ptr(w), _ptr(p),
                                            _ptr(rw), _ptr(rr), norms), "gkb_residual")
         return list(norms), rw, rr
+
+
+from .cnn import CNN  # noqa: E402

@@ -16,17 +16,6 @@ INNER = {"jacobi": 0, "mg": 1, "learned": 2}
 OPS = {"W": 0, "A": 1, "AT": 2, "M": 3, "diag": 4}
 KERNELS = {"smooth": 0, "apply": 1, "resid": 2}
 
-# every symbol declared in include/gkb.h
-EXPORTS = [
-    "gkb_default_options", "gkb_setup", "gkb_solve", "gkb_stats", "gkb_sizes",
-    "gkb_strerror", "gkb_destroy", "gkb_apply", "gkb_precondition",
-    "gkb_inner_solve", "gkb_residual",
-    "gkb_cnn_create", "gkb_cnn_destroy", "gkb_cnn_set_params", "gkb_cnn_get_params",
-    "gkb_cnn_forward", "gkb_cnn_backward", "gkb_cnn_adam_step", "gkb_cnn_attach",
-    "gkb_capture_pairs",
-]
-
-
 class Grid(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("h", C.c_double),
                 ("bc", C.c_int * 6), ("pin_cell", C.c_int)]
@@ -97,28 +86,37 @@ def lib():
 
 def _declare_cnn(L):
     P = C.c_void_p
-    if not hasattr(L, "gkb_cnn_create"):
-        return
-    L.gkb_cnn_create.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.c_void_p,
-                                 C.POINTER(C.c_void_p)]
-    L.gkb_cnn_create.restype = C.c_int
+    I = C.c_int
+    L.gkb_cnn_create.argtypes = [I, I, C.POINTER(I), C.c_uint, C.POINTER(P)]
+    L.gkb_cnn_create.restype = I
     L.gkb_cnn_destroy.argtypes = [P]
     L.gkb_cnn_destroy.restype = None
+    L.gkb_cnn_param_count.argtypes = [P]
+    L.gkb_cnn_param_count.restype = C.c_long
     L.gkb_cnn_set_params.argtypes = [P, P]
-    L.gkb_cnn_set_params.restype = C.c_int
+    L.gkb_cnn_set_params.restype = I
     L.gkb_cnn_get_params.argtypes = [P, P]
-    L.gkb_cnn_get_params.restype = C.c_int
-    L.gkb_cnn_forward.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, P, P]
-    L.gkb_cnn_forward.restype = C.c_int
-    L.gkb_cnn_backward.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int, P, P, P, P]
-    L.gkb_cnn_backward.restype = C.c_int
-    L.gkb_cnn_adam_step.argtypes = [P, P, C.c_double, C.c_double, C.c_double, C.c_double,
-                                    C.c_int]
-    L.gkb_cnn_adam_step.restype = C.c_int
-    L.gkb_cnn_attach.argtypes = [P, P, C.c_double]
-    L.gkb_cnn_attach.restype = C.c_int
-    L.gkb_capture_pairs.argtypes = [P, P, C.c_int, P, C.c_int, P, P, C.POINTER(C.c_int)]
-    L.gkb_capture_pairs.restype = C.c_int
+    L.gkb_cnn_get_params.restype = I
+    L.gkb_cnn_forward.argtypes = [P, I, I, I, I, P, P]
+    L.gkb_cnn_forward.restype = I
+    L.gkb_cnn_backward.argtypes = [P, I, I, I, I, P, P, P, P]
+    L.gkb_cnn_backward.restype = I
+    L.gkb_cnn_adam_step.argtypes = [P, P, C.c_double, C.c_double, C.c_double, C.c_double]
+    L.gkb_cnn_adam_step.restype = I
+    L.gkb_cnn_train.argtypes = [P, P, P, I, I, I, I, I, I, I, C.c_double, C.c_uint, P]
+    L.gkb_cnn_train.restype = I
+    L.gkb_cnn_eval.argtypes = [P, P, P, I, I, I, I, C.POINTER(C.c_double)]
+    L.gkb_cnn_eval.restype = I
+    L.gkb_cnn_save.argtypes = [P, C.c_char_p]
+    L.gkb_cnn_save.restype = I
+    L.gkb_cnn_load.argtypes = [C.c_char_p, C.POINTER(P)]
+    L.gkb_cnn_load.restype = I
+    L.gkb_attach_cnn.argtypes = [P, P]
+    L.gkb_attach_cnn.restype = I
+    L.gkb_set_capture.argtypes = [P, P, P, I, I, P]
+    L.gkb_set_capture.restype = I
+    L.gkb_capture_count.argtypes = [P, C.POINTER(I)]
+    L.gkb_capture_count.restype = I
 
 
 def check(rc: int, what: str = "gkb"):

@@ -21,7 +21,7 @@ FLAGS = [
 
 
 def sources():
-    return [os.path.join(CSRC, "gkb.hip"), os.path.join(CSRC, "cnn.hip")]
+    return [os.path.join(CSRC, "gkb.hip")]
 
 
 def build_library(verbose: bool = False) -> str:

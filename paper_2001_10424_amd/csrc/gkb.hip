@@ -26,6 +26,7 @@
 
 #include "../../include/gkb.h"
 #include "kernels.hpp"
+#include "cnn.hpp"
 #include "learned.hpp"
 #include "tile3d.hpp"
 
@@ -391,6 +392,8 @@ template <typename T>
 int inner_solve(gkb_ctx* c, const double* f, double* x_out, double tol, int* iters) {
   Inner<T>& in = inner_of<T>(c);
   if (!in.ready) return GKB_EINVAL;
+  if (learned_capturing(c->learned) && c->opt.inner != GKB_INNER_JACOBI)
+    return capture_solve<T>(c, f, x_out, tol, iters);
   if (c->opt.inner == GKB_INNER_LEARNED && c->learned && learned_enabled(c->learned))
     return learned_solve<T>(c, f, x_out, tol, iters);
   const Level<T>& L0 = in.lv[0];
@@ -796,6 +799,8 @@ int setup_impl(gkb_ctx* c, const gkb_grid* grid, const double* visc, double eta,
   for (int l = 0; l < L; ++l) {
     maxp = std::max(maxp, face_launch(c->grids[l], 4, c->opt.stencil).nparts);
     maxp = std::max(maxp, face_launch(c->grids[l], 4, 1).nparts);
+    const dim3 tg = transfer_grid(c->grids[l]);  // learned unpack partials
+    maxp = std::max(maxp, (int)(tg.x * tg.z));
     maxp = std::max(maxp, cell_parts(c->grids[l]));
     maxp = std::max(maxp, vec_blocks(c->grids[l].m_full));
   }
@@ -880,7 +885,7 @@ int setup_impl(gkb_ctx* c, const gkb_grid* grid, const double* visc, double eta,
   }
   if (opt->precision == GKB_MIXED) CK(build_inner<float>(c, c->in32, c->coef32));
   else CK(build_inner<double>(c, c->in64, c->coef64));
-  if (opt->inner == GKB_INNER_LEARNED) CK(learned_create(c));
+  if (opt->inner != GKB_INNER_JACOBI) CK(learned_create(c));
   HIPCK(hipStreamSynchronize(c->cs));
   c->stats = gkb_stats_t{};
   return GKB_OK;

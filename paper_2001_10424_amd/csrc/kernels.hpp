@@ -56,8 +56,18 @@ __global__ __launch_bounds__(kFinal) void k_sum_partials(const double* part, int
 
 struct PcgState {
   double rz, pq, alpha, beta, rr, rr0, tol2;
-  double rz_prev;  // flexible CG
-  int it, maxit, done, status, nonfinite, pad;
+  double rz_prev;   // flexible CG
+  double rt2;       // squared norm of the post-V-cycle residual (learned path)
+  double theta;     // energy-optimal weight of the network correction
+  double ring[10];  // r.r of the last 10 iterations (stagnation test)
+  int it, maxit, done, status, nonfinite;
+  int fallback;     // learned preconditioner switched off for this solve
+  int stagnant;     // no decrease of r.r over the last 10 iterations
+  int use_zv;       // direction from the V-cycle alone
+  int fallbacks;
+  int fb_it;        // iteration and cause (1 descent, 2 stagnation) of the fallback
+  int fb_reason;
+  int pad;
 };
 
 // ------------------------------------------------- face-operator kernels
@@ -377,6 +387,10 @@ __global__ __launch_bounds__(kFinal) void k_pcg_start(PcgState* st, const double
     st->nonfinite = 0;
     st->done = (ff == 0.0) ? 1 : 0;
     st->status = 0;
+    st->fallback = st->stagnant = st->use_zv = st->fallbacks = 0;
+    st->fb_it = st->fb_reason = 0;
+    st->theta = 0.0;
+    for (int i = 0; i < 10; ++i) st->ring[i] = 0.0;
   }
 }
 
@@ -445,6 +459,13 @@ __global__ __launch_bounds__(kFinal) void k_pcg_check(PcgState* st, const double
   if (threadIdx.x == 0) {
     st->rr = rr;
     st->it += 1;
+    // r.r sampled every 5 iterations: stagnant when no decrease over 50
+    // (CG minimises the energy norm, so r.r may rise over shorter spans)
+    if (st->it % 5 == 0) {
+      const int slot = (st->it / 5) % 10;
+      if (st->it > 50 && rr >= st->ring[slot]) st->stagnant = 1;
+      st->ring[slot] = rr;
+    }
     if (!isfinite(rr)) {
       st->nonfinite = 1;
       st->status = -4;

@@ -9,8 +9,11 @@ struct Learned;
 
 namespace {
 bool learned_enabled(Learned* L);
+bool learned_capturing(Learned* L);
 template <typename T>
 int learned_solve(gkb_ctx* c, const double* f, double* x_out, double tol, int* iters);
+template <typename T>
+int capture_solve(gkb_ctx* c, const double* f, double* x_out, double tol, int* iters);
 int learned_create(gkb_ctx* c);
 void learned_destroy(gkb_ctx* c);
 }  // namespace

@@ -1,0 +1,216 @@
+"""The learned preconditioner on the GPU: BF16-MFMA convolution forward and
+gradients against the FP64 CPU reference (oracle/cnn_ref.py), the Adam step
+against torch.optim.Adam on the CPU, pair capture and training, and the
+learned flexible-CG inner solve with its multigrid fallback."""
+import numpy as np
+import pytest
+
+import oracle
+import problems as P
+from oracle import cnn_ref
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _gk():
+    import paper_2001_10424_amd as gk
+    return gk
+
+
+def bf16(a):
+    """Round to BF16 (nearest even), returned as float64."""
+    u = np.ascontiguousarray(np.asarray(a, dtype=np.float32)).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _ref_forward_bf16(x, params, dim, channels):
+    """Reference forward with the GPU's storage precision: BF16 input,
+    weights and hidden activations; FP32 bias and FP64 sums."""
+    layers = cnn_ref.unflatten(params, dim, channels)
+    a = bf16(x)
+    for l, (W, b) in enumerate(layers):
+        z = cnn_ref.conv(a, bf16(W), np.asarray(b, np.float32).astype(np.float64), dim)
+        if l < len(layers) - 1:
+            a = bf16(np.maximum(z, 0.0))
+        else:
+            a = z
+    return a
+
+
+CASES = [(2, (3, 16, 16, 16, 2), (2, 24, 40)), (3, (4, 8, 8, 3), (2, 12, 10, 17)),
+         (3, (4, 16, 3), (1, 9, 16, 33))]
+
+
+@pytest.mark.parametrize("dim,channels,shape", CASES)
+def test_forward_matches_reference(dim, channels, shape):
+    _say("cnn forward", dim, channels)
+    import torch
+    gk = _gk()
+    rng = np.random.default_rng(0)
+    net = gk.CNN(dim, channels, seed=3)
+    params = net.params.astype(np.float64)
+    params += 0.05 * rng.standard_normal(params.size)  # non-zero biases
+    net.params = params.astype(np.float32)
+    params = net.params.astype(np.float64)
+    x = rng.standard_normal(shape + (channels[0],)).astype(np.float32)
+    y = net.forward(torch.tensor(x, device="cuda")).cpu().numpy()
+    ref = _ref_forward_bf16(x, params, dim, channels)
+    err = np.abs(y - ref).max() / np.abs(ref).max()
+    assert err <= 1e-2, err
+    # one layer: only the FP32 accumulation order differs
+    one = gk.CNN(dim, (channels[0], channels[1]), seed=5)
+    p1 = one.params.astype(np.float64)
+    y1 = one.forward(torch.tensor(x, device="cuda")).cpu().numpy()
+    W, b = cnn_ref.unflatten(p1, dim, (channels[0], channels[1]))[0]
+    r1 = cnn_ref.conv(bf16(x), bf16(W), b, dim)
+    assert np.abs(y1 - r1).max() <= 1e-5 * np.abs(r1).max()
+
+
+@pytest.mark.parametrize("dim,channels,shape", CASES[:2])
+def test_gradients_match_reference(dim, channels, shape):
+    _say("cnn backward", dim, channels)
+    import torch
+    gk = _gk()
+    rng = np.random.default_rng(1)
+    net = gk.CNN(dim, channels, seed=7)
+    params = net.params.astype(np.float64)
+    x = rng.standard_normal(shape + (channels[0],)).astype(np.float32)
+    e = rng.standard_normal(shape + (channels[-1],)).astype(np.float32)
+    y = net.forward(torch.tensor(x, device="cuda")).cpu().numpy()
+    dy = cnn_ref.loss_grad(y, e).astype(np.float32)
+    g, dx = net.backward(torch.tensor(x, device="cuda"), torch.tensor(dy, device="cuda"))
+    gr, dxr = cnn_ref.backward(bf16(x), bf16(params), dim, channels, bf16(dy))
+    # BF16 hidden activations and ReLU masks that flip at the rounding level
+    # make the multi-layer comparison loose; the one-layer check below is tight
+    eg = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    ex = np.linalg.norm(dx.cpu().numpy() - dxr) / np.linalg.norm(dxr)
+    assert eg <= 2e-2 and ex <= 6e-2, (eg, ex)
+    # per layer: weight and bias blocks each agree
+    o = 0
+    taps = 9 if dim == 2 else 27
+    for ci, co in zip(channels[:-1], channels[1:]):
+        nwb = taps * ci * co + co
+        blk = slice(o, o + nwb)
+        assert np.linalg.norm(g[blk] - gr[blk]) <= 5e-2 * np.linalg.norm(gr[blk])
+        o += nwb
+    # one layer (no mask): BF16 operands are exact in the reference, so only
+    # the FP32 accumulation order differs
+    one = gk.CNN(dim, (channels[0], channels[1]), seed=11)
+    p1 = one.params.astype(np.float64)
+    y1 = one.forward(torch.tensor(x, device="cuda")).cpu().numpy()
+    e1 = rng.standard_normal(y1.shape).astype(np.float32)
+    d1 = bf16(cnn_ref.loss_grad(y1, e1)).astype(np.float32)
+    g1, dx1 = one.backward(torch.tensor(x, device="cuda"), torch.tensor(d1, device="cuda"))
+    gr1, dxr1 = cnn_ref.backward(bf16(x), bf16(p1), dim, (channels[0], channels[1]), d1)
+    assert np.linalg.norm(g1 - gr1) <= 1e-5 * np.linalg.norm(gr1)
+    assert np.linalg.norm(dx1.cpu().numpy() - dxr1) <= 1e-5 * np.linalg.norm(dxr1)
+
+
+def test_adam_matches_torch():
+    _say("adam")
+    import torch
+    gk = _gk()
+    net = gk.CNN(2, (3, 4, 2), seed=1)
+    p0 = net.params.copy()
+    rng = np.random.default_rng(2)
+    grads = [rng.standard_normal(p0.size).astype(np.float32) for _ in range(3)]
+    w = torch.tensor(p0.copy(), requires_grad=True)
+    opt = torch.optim.Adam([w], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    for gvec in grads:
+        net.adam_step(gvec, lr=1e-2)
+        opt.zero_grad()
+        w.grad = torch.tensor(gvec)
+        opt.step()
+    np.testing.assert_allclose(net.params, w.detach().numpy(), rtol=1e-5, atol=1e-6)
+
+
+def test_checkpoint_roundtrip(tmp_path):
+    _say("checkpoint")
+    gk = _gk()
+    net = gk.CNN(3, (4, 8, 3), seed=9)
+    net.adam_step(np.ones(net.n_params, np.float32), lr=1e-3)
+    path = str(tmp_path / "w.bin")
+    net.save(path)
+    other = gk.CNN.load(path)
+    assert np.array_equal(other.params, net.params)
+
+
+def _small_problem(seed, n=32):
+    return P.stokes_problem(3, n, seed=seed, eta=1e3, lid=True)
+
+
+def _solver(gk, pr, inner="learned", **kw):
+    opts = dict(precision="mixed", inner=inner, inner_tol=1e-5, refine_tol=1e-8, max_sweeps=12,
+                maxit=200, inner_maxit=5000)
+    opts.update(kw)
+    return gk.Solver(pr.grid, pr.mu, pr.eta, **opts)
+
+
+def _dev(x):
+    import torch
+    return torch.tensor(np.asarray(x), device="cuda")
+
+
+def test_capture_train_and_learned_solve():
+    """Pairs captured from MG-PCG inner solves train the network (loss
+    falls); the learned FCG solve meets the FP64 residual target checked by
+    the oracle; the iteration counts with and without the network are
+    reported."""
+    _say("capture/train/solve")
+    from paper_2001_10424_amd.cnn import capture_pairs
+    gk = _gk()
+    ins, tgs = [], []
+    for seed in (101, 102):
+        pr = _small_problem(seed)
+        s = _solver(gk, pr, inner="mg")
+        a, b = capture_pairs(s, _dev(pr.g), _dev(pr.r), tol=1e-4, max_pairs=40)
+        ins.append(a)
+        tgs.append(b)
+        s.close()
+    import torch
+    inputs = torch.cat(ins).contiguous()
+    targets = torch.cat(tgs).contiguous()
+    assert inputs.shape[0] >= 20 and torch.isfinite(inputs).all() and torch.isfinite(targets).all()
+    net = gk.CNN(3, (4, 8, 8, 3), seed=0)
+    before = net.evaluate(inputs, targets, (32, 32, 32))
+    losses = net.train(inputs, targets, (32, 32, 32), crop=16, batch=8, steps=150, lr=3e-3, seed=1)
+    after = net.evaluate(inputs, targets, (32, 32, 32))
+    print(f"loss before {before:.4f} after {after:.4f}", flush=True)
+    assert np.isfinite(losses).all() and after < 0.9 * before
+    pr = _small_problem(7)
+    res = {}
+    for inner in ("mg", "learned"):
+        s = _solver(gk, pr, inner=inner)
+        if inner == "learned":
+            s.attach_cnn(net)
+        w, p, info = s.solve(_dev(pr.g), _dev(pr.r), tol=1e-4)
+        _, _, nr = oracle.saddle_residual(pr.grid, pr.g, pr.r, w.cpu().numpy(), p.cpu().numpy())
+        assert nr[0] <= 1e-8 * nr[3]
+        res[inner] = info
+        s.close()
+    print("inner iterations mg", res["mg"]["inner_iterations"], "learned",
+          res["learned"]["inner_iterations"], "fallbacks", res["learned"]["fallbacks"], flush=True)
+
+
+def test_sabotaged_network_falls_back_and_converges():
+    """Sign-flipped output weights make the correction point uphill: the
+    descent / progress guards switch to MG-PCG and the solve still meets the
+    FP64 residual target."""
+    _say("sabotage")
+    gk = _gk()
+    net = gk.CNN(3, (4, 8, 3), seed=4)
+    p = net.params
+    net.params = -50.0 * p
+    pr = _small_problem(8, n=16)
+    s = _solver(gk, pr)
+    s.attach_cnn(net)
+    w, pp, info = s.solve(_dev(pr.g), _dev(pr.r), tol=1e-4)
+    _, _, nr = oracle.saddle_residual(pr.grid, pr.g, pr.r, w.cpu().numpy(), pp.cpu().numpy())
+    assert nr[0] <= 1e-8 * nr[3]
+    assert info["fallbacks"] > 0
+    s.close()
