@@ -3,15 +3,21 @@ problem on a 128^3 MAC grid (eta = 1e3) to an FP64 relative saddle residual
 of 1e-8, on one MI355X.
 
 A step is one complete gkb_solve (transformation, outer GKB recurrence, all
-inner multigrid-preconditioned solves, FP64 residual checks and
-defect-correction sweeps) on inputs already resident in HBM.
+inner preconditioned solves, FP64 residual checks and defect-correction
+sweeps) on inputs already resident in HBM.  Three solver configurations of
+the same problem are timed:
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--mode mixed_mg]
+  mixed_learned  FP32 inner flexible CG with V-cycle + CNN correction
+                 (MG-PCG fallback), FP64 GKB recurrence and residual
+  mixed_mg       FP32 inner MG-PCG, FP64 GKB recurrence and residual
+  fp64_mg        FP64 everywhere (plain multigrid GKB)
 
-Prints one JSON line.  Besides the headline mode it times the FP64
-multigrid-GKB solve of the same problem (--compare), the dominant kernel's
-achieved bandwidth against the HBM roofline, and the CPU oracle on a bounded
-sample (cpu_baseline).
+`value` is the time of --mode (default mixed_learned); the others are in
+config.compare_seconds.  The CNN of the learned mode is trained first on
+pairs captured from MG-PCG inner solves of a different forcing (seed 1000);
+capture and training time are reported apart from the solve time.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--mode mixed_learned]
 """
 from __future__ import annotations
 
@@ -33,25 +39,52 @@ MODES = {
     "mixed_mg": ("mixed", "mg", 1e-4, 1e-5),
     "mixed_learned": ("mixed", "learned", 1e-4, 1e-5),
 }
+CNN_CHANNELS = (4, 8, 8, 3)  # 3 conv3x3x3 layers, 8 hidden channels
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_solver(gk, pr, mode, weights=None):
+def make_solver(gk, pr, mode, net=None):
     prec, inner, _, itol = MODES[mode]
     kw = dict(precision=prec, inner=inner, nu_pre=2, nu_post=2, inner_tol=itol,
               inner_maxit=5000, maxit=200, refine_tol=1e-8, max_sweeps=12, check_every=8)
     s = gk.Solver(pr.grid, pr.mu, pr.eta, **kw)
     if inner == "learned":
-        s.attach_cnn(weights)
+        s.attach_cnn(net)
     return s
 
 
-def time_mode(gk, torch, pr, mode, steps, warmup, g, r, weights=None):
+def train_cnn(gk, torch, problems, n, weights=None):
+    """Pairs from the MG-PCG inner solves of a mixed-precision GKB solve of
+    the same grid with forcing seed 1000, then Adam on 32^3 crops."""
+    from paper_2001_10424_amd.cnn import capture_pairs
+    if weights:
+        return gk.CNN.load(weights), {"weights": weights}
     t0 = time.perf_counter()
-    s = make_solver(gk, pr, mode, weights)
+    pr = problems.stokes_problem(3, n, seed=1000, eta=1e3, lid=True)
+    s = make_solver(gk, pr, "mixed_mg")
+    inp, tgt = capture_pairs(s, torch.tensor(pr.g, device="cuda"),
+                             torch.tensor(pr.r, device="cuda"), tol=1e-4, max_pairs=32)
+    s.close()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    net = gk.CNN(3, CNN_CHANNELS, seed=0)
+    crop = min(32, n)
+    loss0 = net.evaluate(inp, tgt, (n, n, n))
+    losses = net.train(inp, tgt, (n, n, n), crop=crop, batch=8, steps=300, lr=2e-3, seed=1)
+    loss1 = net.evaluate(inp, tgt, (n, n, n))
+    t2 = time.perf_counter()
+    del inp, tgt
+    return net, {"pairs_s": round(t1 - t0, 3), "train_s": round(t2 - t1, 3), "steps": 300,
+                 "loss_before": round(loss0, 5), "loss_after": round(loss1, 5),
+                 "loss_last": round(float(losses[-1]), 5)}
+
+
+def time_mode(gk, torch, pr, mode, steps, warmup, g, r, net=None):
+    t0 = time.perf_counter()
+    s = make_solver(gk, pr, mode, net)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     tol = MODES[mode][2]
@@ -75,10 +108,10 @@ def time_mode(gk, torch, pr, mode, steps, warmup, g, r, weights=None):
 
 def cpu_baseline(pr):
     """The CPU FP64 oracle (GKB + Jacobi-PCG) on a bounded sample: 20
-    Jacobi-PCG iterations on the full 128^3 problem (seconds per iteration),
-    and one complete oracle solve of the same problem at 16^3 (iteration
-    count); the iteration count is projected to 128^3 with the growth
-    exponent measured between 8^3 and 16^3 full oracle solves."""
+    Jacobi-PCG iterations on the full problem (seconds per iteration), and
+    complete oracle solves of the same problem family at 8^3 and 16^3 (inner
+    iteration counts); the count is projected to the full grid with the
+    growth exponent measured between those two sizes."""
     import math
 
     import oracle
@@ -87,11 +120,10 @@ def cpu_baseline(pr):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     oracle.lib()
     t0 = time.perf_counter()
-    res = oracle.gkb_solve(pr.grid, pr.g, pr.r, pr.eta, mu=pr.mu, tol=1e-9, delay=5, maxit=1,
-                           inner_tol=1e-10, inner_maxit=20)
+    oracle.gkb_solve(pr.grid, pr.g, pr.r, pr.eta, mu=pr.mu, tol=1e-9, delay=5, maxit=1,
+                     inner_tol=1e-10, inner_maxit=20)
     t_iter = (time.perf_counter() - t0) / 20.0
-    its = {}
-    t_small = {}
+    its, t_small = {}, {}
     for n in (8, 16):
         sp = problems.stokes_problem(3, n, seed=0, eta=pr.eta, lid=True)
         t1 = time.perf_counter()
@@ -102,14 +134,12 @@ def cpu_baseline(pr):
     expo = math.log(its[16] / its[8]) / math.log(2.0)
     n_big = pr.grid.n[0]
     its_big = its[16] * (n_big / 16.0) ** expo
-    projected = t_iter * its_big
-    del res
-    return {"value": projected, "unit": "s", "cores": threads, "kind": "oracle",
-            "sample": (f"oracle FP64 GKB + Jacobi-PCG: {t_iter:.3f} s per inner iteration "
-                       f"measured over 20 iterations at {n_big}^3; full oracle solves at "
-                       f"8^3 / 16^3 took {its[8]} / {its[16]} inner iterations "
-                       f"({t_small[8]:.1f} s / {t_small[16]:.1f} s); projected "
-                       f"{its_big:.3g} iterations at {n_big}^3 (growth n^{expo:.2f})")}
+    return {"value": round(t_iter * its_big, 1), "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": (f"projection: oracle FP64 GKB + Jacobi-PCG took {t_iter:.3f} s per inner "
+                       f"iteration over 20 iterations at {n_big}^3; full oracle solves at 8^3 / "
+                       f"16^3 needed {its[8]} / {its[16]} inner iterations "
+                       f"({t_small[8]:.1f} s / {t_small[16]:.1f} s), growth n^{expo:.2f}, "
+                       f"projected {its_big:.3g} iterations at {n_big}^3")}
 
 
 def main():
@@ -117,19 +147,21 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", default="mixed_mg", choices=list(MODES))
+    ap.add_argument("--mode", default="mixed_learned", choices=list(MODES))
     ap.add_argument("--n", type=int, default=128, help="cells per axis of the 3D problem")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--weights", default=None, help="CNN weights for mixed_learned")
+    ap.add_argument("--weights", default=None, help="CNN checkpoint for mixed_learned")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only the calibration copy and 20 launches of the dominant kernel "
+                         "(hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this solver build has no multi-GPU path "
+        print("bench.py measures one GPU only: this solver has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import problems
@@ -141,30 +173,53 @@ def main():
     r = torch.tensor(pr.r, device="cuda")
     log(f"[bench] workload stokes3d_{args.n}_lid m={pr.grid.m} n={pr.grid.n_p}")
 
-    s, w, p, main_res = time_mode(gk, torch, pr, args.mode, args.steps, args.warmup, g, r,
-                                  args.weights)
+    # calibration copy of known size for the HBM counters (256 MiB read +
+    # 256 MiB written): one torch copy kernel in every profiled run
+    cal_src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+    cal_dst = torch.empty_like(cal_src)
+    cal_dst.copy_(cal_src)
+    torch.cuda.synchronize()
+    del cal_src, cal_dst
+
+    if args.kernel_only:
+        # counter runs: the calibration copy above plus launches of the
+        # dominant kernel on the buffers of one inner solve
+        s = make_solver(gk, pr, "mixed_mg")
+        s.inner_solve(g, 1e-3)
+        ms = s.time_kernel("smooth", 20)
+        print(json.dumps({"kernel_only": True, "smooth_avg_ms": ms, "m_full": s.m_full}))
+        s.close()
+        return
+
+    net, train_info = None, None
+    if MODES[args.mode][1] == "learned":
+        net, train_info = train_cnn(gk, torch, problems, args.n, args.weights)
+        log(f"[bench] cnn {json.dumps(train_info)}")
+
+    s, w, p, main_res = time_mode(gk, torch, pr, args.mode, args.steps, args.warmup, g, r, net)
     log(f"[bench] {args.mode}: {json.dumps(main_res)}")
     compare = {args.mode: main_res}
     if not args.no_compare:
-        for m in ("fp64_mg", "mixed_mg"):
-            if m == args.mode:
+        for m in ("fp64_mg", "mixed_mg", "mixed_learned"):
+            if m == args.mode or (m == "mixed_learned" and net is None):
                 continue
-            s2, _, _, res2 = time_mode(gk, torch, pr, m, args.steps, args.warmup, g, r)
+            s2, _, _, res2 = time_mode(gk, torch, pr, m, args.steps, args.warmup, g, r, net)
             compare[m] = res2
             s2.close()
             log(f"[bench] {m}: {json.dumps(res2)}")
 
     # dominant kernel: the finest-grid weighted-Jacobi sweep of the inner
-    # solve (reads x and b, writes y: 3 full-face vectors per launch)
+    # solve, k_tile3d<T, false, kJacobi, true> (reads x and b, writes y: three
+    # full-face vectors per launch)
     elem = 4 if MODES[args.mode][0] == "mixed" else 8
-    reps = 50
-    ms = s.time_kernel("smooth", reps)
+    ms = s.time_kernel("smooth", 100)
     bytes_per_launch = 3 * s.m_full * elem
     achieved = bytes_per_launch / (ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_face_op<kJacobi> finest grid", "avg_ms": round(ms, 5),
-                "bytes_per_launch": bytes_per_launch}
+                "kernel": "k_tile3d<float,false,kJacobi,fine> (finest-grid Jacobi sweep)"
+                if elem == 4 else "k_tile3d<double,false,kJacobi,fine>",
+                "avg_ms": round(ms, 5), "bytes_per_launch": bytes_per_launch}
     s.close()
 
     cpu = None
@@ -189,14 +244,15 @@ def main():
                                f"lid u=1 on +z, 8-mode Fourier body force (seed {args.seed}), "
                                f"eta=1e3, stop at FP64 relative saddle residual 1e-8",
                    "mode": args.mode,
-                   "inner": "PCG with geometric MG V(2,2), weighted Jacobi, FP64 coarsest",
+                   "inner": "PCG / flexible CG with geometric MG V(2,2), weighted Jacobi, "
+                            "5 levels, FP64 dense coarsest solve",
                    "compare_seconds": {k: round(v["seconds"], 5) for k, v in compare.items()},
-                   "details": compare},
+                   "details": compare,
+                   "cnn_training": train_info},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    del w, p, np
 
 
 if __name__ == "__main__":

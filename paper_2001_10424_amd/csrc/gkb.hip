@@ -79,7 +79,11 @@ FaceLaunch face_launch(const Grid& g, int kz, int stencil = 0) {
   // the tiled kernel covers the lower faces of every cell: the upper faces
   // must be Dirichlet (zero) faces
   const bool upper_dir = g.bc[1] == kDir && g.bc[3] == kDir && g.bc[5] == kDir;
-  if (stencil == 0 && g.dim == 3 && upper_dir) {
+  static const long tile_min = [] {
+    const char* e = std::getenv("GKB_TILE_MIN");
+    return e ? std::atol(e) : 0L;
+  }();
+  if (stencil == 0 && g.dim == 3 && upper_dir && g.n_cells >= tile_min) {
     if (g_tz == 0) {
       const char* e = std::getenv("GKB_TZ");
       g_tz = e ? std::max(1, std::atoi(e)) : -1;
@@ -212,8 +216,14 @@ void face_op(gkb_ctx* c, const Op<T>& op, const FaceLaunch& fl, const T* x, cons
   const int kz = fl.kz, zc = fl.zchunks;
   hipStream_t s = c->cs;
   if (fl.tiled && MODE != kJacobi0 && MODE != kDiag) {
-    if (vm) k_tile3d<T, true, MODE><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st);
-    else k_tile3d<T, false, MODE><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st);
+    const bool fine = op.g.m_full == c->g.m_full;
+    if (vm) {
+      if (fine) k_tile3d<T, true, MODE, true><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st);
+      else k_tile3d<T, true, MODE, false><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st);
+    } else {
+      if (fine) k_tile3d<T, false, MODE, true><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st);
+      else k_tile3d<T, false, MODE, false><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st);
+    }
     return;
   }
   if (op.g.dim == 2) {

@@ -84,7 +84,9 @@ __device__ __forceinline__ double tile_finish(int f, T mx, T d, T xf, T bf, T* _
   return part;
 }
 
-template <typename T, bool VARMU, int MODE>
+// FINE only separates the finest-grid launches from the coarse-level ones in
+// kernel traces; the code is the same
+template <typename T, bool VARMU, int MODE, bool FINE>
 __global__ __launch_bounds__(256) void k_tile3d(Op<T> op, const T* __restrict__ x,
                                                 const T* __restrict__ b, T* __restrict__ y,
                                                 T omega, int tz, double* __restrict__ partial,
@@ -105,21 +107,43 @@ __global__ __launch_bounds__(256) void k_tile3d(Op<T> op, const T* __restrict__ 
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const bool unk_u0 = G.bc[0] == kNat, unk_v0 = G.bc[2] == kNat, unk_w0 = G.bc[4] == kNat;
 
-  auto load_plane = [&](int k, int s) {
-    for (int e = threadIdx.x; e < kLX * kLY; e += 256) {
-      const int jj = e / kLX, ii = e - jj * kLX;
-      const int i = i0 - 1 + ii, j = j0 - 1 + jj;
-      T uu = T(0), vv = T(0), ww = T(0);
-      const bool jin = j >= 0 && j < ny, iin = i >= 0 && i < nx;
-      if (k >= 0 && k < nz) {
-        if (jin && i >= 0 && i < nx && (i > 0 || unk_u0)) uu = x[fidx<0>(G, i, j, k)];
-        if (iin && j >= 0 && j < ny && (j > 0 || unk_v0)) vv = x[fidx<1>(G, i, j, k)];
+  // plane staging is split into a global fetch into registers and an LDS
+  // store, so that the fetch of plane k+2 is in flight while plane k is
+  // computed
+  constexpr int kPer = (kLX * kLY + 255) / 256;
+  T fu[kPer], fv[kPer], fw[kPer];
+  auto fetch_plane = [&](int k) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = threadIdx.x + q * 256;
+      fu[q] = fv[q] = fw[q] = T(0);
+      if (e < kLX * kLY) {
+        const int jj = e / kLX, ii = e - jj * kLX;
+        const int i = i0 - 1 + ii, j = j0 - 1 + jj;
+        const bool jin = j >= 0 && j < ny, iin = i >= 0 && i < nx;
+        if (k >= 0 && k < nz) {
+          if (jin && iin && (i > 0 || unk_u0)) fu[q] = x[fidx<0>(G, i, j, k)];
+          if (iin && jin && (j > 0 || unk_v0)) fv[q] = x[fidx<1>(G, i, j, k)];
+          if (iin && jin && (k > 0 || unk_w0)) fw[q] = x[fidx<2>(G, i, j, k)];
+        }
       }
-      if (k >= 0 && k < nz && iin && jin && (k > 0 || unk_w0)) ww = x[fidx<2>(G, i, j, k)];
-      S.u[s][jj][ii] = uu;
-      S.v[s][jj][ii] = vv;
-      S.w[s][jj][ii] = ww;
     }
+  };
+  auto store_plane = [&](int s) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = threadIdx.x + q * 256;
+      if (e < kLX * kLY) {
+        const int jj = e / kLX, ii = e - jj * kLX;
+        S.u[s][jj][ii] = fu[q];
+        S.v[s][jj][ii] = fv[q];
+        S.w[s][jj][ii] = fw[q];
+      }
+    }
+  };
+  auto load_plane = [&](int k, int s) {
+    fetch_plane(k);
+    store_plane(s);
   };
   auto cell_ok = [&](int i, int j, int k) {
     return i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz && cidx(G, i, j, k) != G.pin;
@@ -142,12 +166,14 @@ __global__ __launch_bounds__(256) void k_tile3d(Op<T> op, const T* __restrict__ 
                  : T(0);
   }
   __syncthreads();
+  fetch_plane(k0 + 1);
 
   const T eta = op.eta, ih2 = op.ih2;
   double part = 0.0;
   for (int k = k0; k < k1; ++k) {
     const int s = (k - k0) & 1, s1 = s ^ 1;
-    // b of this thread's faces, issued together with the plane loads
+    store_plane(s1);  // plane k+1, fetched during the previous plane
+    // b of this thread's faces
     T bu[kRPT], bv[kRPT], bw[kRPT];
 #pragma unroll
     for (int r = 0; r < kRPT; ++r) {
@@ -159,8 +185,8 @@ __global__ __launch_bounds__(256) void k_tile3d(Op<T> op, const T* __restrict__ 
         bw[r] = b[fidx<2>(G, i, j, k)];
       }
     }
-    load_plane(k + 1, s1);
     __syncthreads();
+    if (k + 1 < k1) fetch_plane(k + 2);  // consumed at the top of the next plane
     // divergence sums of plane k for cells (i0-1 .. i0+63) x (j0-1 .. j0+7)
     for (int e = threadIdx.x; e < (kTX + 1) * (kTY + 1); e += 256) {
       const int cj = e / (kTX + 1), ci = e - cj * (kTX + 1);
