@@ -46,6 +46,38 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+COUNTERS_MD = os.path.join(ROOT, "profiles", "tile3d_jacobi_fp32_128cube_counters.md")
+KERNEL_SOURCES = ("paper_2001_10424_amd/csrc/tile3d.hpp", "paper_2001_10424_amd/csrc/mac.hpp",
+                  "paper_2001_10424_amd/csrc/kernels.hpp")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, or None when the kernel sources changed since
+    the counters were taken."""
+    try:
+        fields = {}
+        with open(COUNTERS_MD) as f:
+            for line in f:
+                if ":" in line and line.startswith("- "):
+                    k, v = line[2:].split(":", 1)
+                    fields[k.strip()] = v.strip().strip("`")
+        if fields.get("source_sha256") != kernel_source_hash():
+            return None
+        return int(float(fields["traffic_bytes_per_launch"]))
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def make_solver(gk, pr, mode, net=None):
     prec, inner, _, itol = MODES[mode]
     kw = dict(precision=prec, inner=inner, nu_pre=2, nu_post=2, inner_tol=itol,
@@ -216,7 +248,8 @@ def main():
     bytes_per_launch = 3 * s.m_full * elem
     achieved = bytes_per_launch / (ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": counter_traffic() if elem == 4 else None,
                 "kernel": "k_tile3d<float,false,kJacobi,fine> (finest-grid Jacobi sweep)"
                 if elem == 4 else "k_tile3d<double,false,kJacobi,fine>",
                 "avg_ms": round(ms, 5), "bytes_per_launch": bytes_per_launch}
