@@ -34,10 +34,16 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 
 MODES = {
-    # name: (precision, inner, gkb tol per sweep, inner tol)
-    "fp64_mg": ("fp64", "mg", 1e-9, 1e-10),
-    "mixed_mg": ("mixed", "mg", 1e-4, 1e-5),
-    "mixed_learned": ("mixed", "learned", 1e-4, 1e-5),
+    # name: (precision, inner, gkb tol per sweep, inner tol, delay).  Every
+    # mode stops on the same FP64 saddle residual (1e-8); the defect-correction
+    # modes run loose GKB sweeps (tau = 1e-2, tau_in = tau / 10, d = 2), the
+    # fastest setting of a sweep over tau in [1e-3, 3e-2] and d in {2, 3} for
+    # FP64 and FP32 inner solves alike.  fp64_gkb1 is the paper's method as
+    # printed: one GKB run whose lower-bound tolerance alone reaches 1e-8.
+    "fp64_mg": ("fp64", "mg", 1e-2, 1e-3, 2),
+    "mixed_mg": ("mixed", "mg", 1e-2, 1e-3, 2),
+    "mixed_learned": ("mixed", "learned", 1e-2, 1e-3, 2),
+    "fp64_gkb1": ("fp64", "mg", 1e-9, 1e-10, 5),
 }
 CNN_CHANNELS = (4, 8, 8, 3)  # 3 conv3x3x3 layers, 8 hidden channels
 
@@ -79,7 +85,7 @@ def counter_traffic():
 
 
 def make_solver(gk, pr, mode, net=None):
-    prec, inner, _, itol = MODES[mode]
+    prec, inner, _, itol, _ = MODES[mode]
     kw = dict(precision=prec, inner=inner, nu_pre=2, nu_post=2, inner_tol=itol,
               inner_maxit=5000, maxit=200, refine_tol=1e-8, max_sweeps=12, check_every=8)
     s = gk.Solver(pr.grid, pr.mu, pr.eta, **kw)
@@ -96,7 +102,10 @@ def train_cnn(gk, torch, problems, n, weights=None):
         return gk.CNN.load(weights), {"weights": weights}
     t0 = time.perf_counter()
     pr = problems.stokes_problem(3, n, seed=1000, eta=1e3, lid=True)
-    s = make_solver(gk, pr, "mixed_mg")
+    # capture runs converge each inner solve to 1e-5 so that the error
+    # targets e_i = x* - x_i are accurate
+    s = gk.Solver(pr.grid, pr.mu, pr.eta, precision="mixed", inner="mg", inner_tol=1e-5,
+                  inner_maxit=5000, maxit=200, refine_tol=1e-8, max_sweeps=12)
     inp, tgt = capture_pairs(s, torch.tensor(pr.g, device="cuda"),
                              torch.tensor(pr.r, device="cuda"), tol=1e-4, max_pairs=32)
     s.close()
@@ -119,14 +128,14 @@ def time_mode(gk, torch, pr, mode, steps, warmup, g, r, net=None):
     s = make_solver(gk, pr, mode, net)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    tol = MODES[mode][2]
+    tol, delay = MODES[mode][2], MODES[mode][4]
     info = None
     for _ in range(warmup):
-        w, p, info = s.solve(g, r, tol=tol, delay=5)
+        w, p, info = s.solve(g, r, tol=tol, delay=delay)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        w, p, info = s.solve(g, r, tol=tol, delay=5)
+        w, p, info = s.solve(g, r, tol=tol, delay=delay)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     norms, _, _ = s.residual(g, r, w, p)
@@ -232,7 +241,7 @@ def main():
     log(f"[bench] {args.mode}: {json.dumps(main_res)}")
     compare = {args.mode: main_res}
     if not args.no_compare:
-        for m in ("fp64_mg", "mixed_mg", "mixed_learned"):
+        for m in ("fp64_mg", "mixed_mg", "mixed_learned", "fp64_gkb1"):
             if m == args.mode or (m == "mixed_learned" and net is None):
                 continue
             s2, _, _, res2 = time_mode(gk, torch, pr, m, args.steps, args.warmup, g, r, net)

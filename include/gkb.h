@@ -109,7 +109,10 @@ typedef struct {
   int outer_iterations;   /* K summed over sweeps */
   long inner_iterations;  /* inner Krylov iterations summed over all solves */
   int inner_solves;
-  int fallbacks;          /* learned -> MG-PCG switches */
+  int fallbacks;          /* learned -> MG-PCG switches inside inner solves */
+  int learned_solves;     /* inner solves run with the network; after two
+                             consecutive solves with a fallback the rest of
+                             the gkb_solve uses MG-PCG */
   double residual;        /* final ||res||_2 / ||[g; r]||_2 (FP64), -1 if not computed */
   double error_estimate;  /* last lower-bound ratio */
   double seconds_solve;   /* wall time of the last gkb_solve */

@@ -131,7 +131,8 @@ class Solver:
         n = st.history_len
         return dict(sweeps=st.sweeps, outer_iterations=st.outer_iterations,
                     inner_iterations=st.inner_iterations, inner_solves=st.inner_solves,
-                    fallbacks=st.fallbacks, residual=st.residual,
+                    fallbacks=st.fallbacks, learned_solves=st.learned_solves,
+                    residual=st.residual,
                     seconds_solve=st.seconds_solve, zeta=list(st.zeta[:n]),
                     estimate=list(st.estimate[:n]), workspace_bytes=st.workspace_bytes,
                     mg_levels=st.mg_levels, omega=list(st.omega[:st.mg_levels]))

@@ -33,7 +33,7 @@ class Options(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("sweeps", C.c_int), ("outer_iterations", C.c_int),
                 ("inner_iterations", C.c_long), ("inner_solves", C.c_int),
-                ("fallbacks", C.c_int), ("residual", C.c_double),
+                ("fallbacks", C.c_int), ("learned_solves", C.c_int), ("residual", C.c_double),
                 ("error_estimate", C.c_double), ("seconds_solve", C.c_double),
                 ("history_len", C.c_int), ("zeta", C.c_double * 512),
                 ("estimate", C.c_double * 512), ("workspace_bytes", C.c_size_t),

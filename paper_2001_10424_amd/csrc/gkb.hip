@@ -986,7 +986,9 @@ int gkb_solve(gkb_ctx* c, const double* g, const double* r, double tol, int dela
   c->stats.inner_iterations = 0;
   c->stats.inner_solves = 0;
   c->stats.fallbacks = 0;
+  c->stats.learned_solves = 0;
   c->stats.residual = -1.0;
+  learned_reset(c->learned);
   int K = 0, rc;
   double est = 0.0;
   if (c->opt.refine_tol <= 0.0) {

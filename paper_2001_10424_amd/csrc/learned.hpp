@@ -10,6 +10,7 @@ struct Learned;
 namespace {
 bool learned_enabled(Learned* L);
 bool learned_capturing(Learned* L);
+void learned_reset(Learned* L);
 template <typename T>
 int learned_solve(gkb_ctx* c, const double* f, double* x_out, double tol, int* iters);
 template <typename T>

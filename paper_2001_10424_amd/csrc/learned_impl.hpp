@@ -9,7 +9,11 @@
 
 struct Learned {
   gkb_cnn* net = nullptr;
-  double lam = 1.0;       // mean diag(M) over the unknown faces
+  // after two consecutive inner solves whose network direction failed the
+  // guards, the rest of the gkb_solve uses MG-PCG
+  int fails = 0;
+  bool off = false;
+  double lam = 1.0;       // mean diag(W) over the unknown faces
   long m_unknown = 1;
   float* logmu = nullptr;  // cell log-viscosity (input channel), zeros for mu = 1
   // FCG work vectors (inner precision stored as raw bytes)
@@ -236,7 +240,13 @@ __global__ __launch_bounds__(256) void k_err_after_v(int n, const T* __restrict_
 
 namespace {
 
-bool learned_enabled(Learned* L) { return L && L->net; }
+bool learned_enabled(Learned* L) { return L && L->net && !L->off; }
+void learned_reset(Learned* L) {
+  if (L) {
+    L->fails = 0;
+    L->off = false;
+  }
+}
 bool learned_capturing(Learned* L) { return L && L->cap_in && L->cap_n < L->cap_max; }
 
 int learned_create(gkb_ctx* c) {
@@ -412,7 +422,13 @@ int learned_solve(gkb_ctx* c, const double* f, double* x_out, double tol, int* i
   if (iters) *iters = hs.it;
   c->stats.inner_iterations += hs.it;
   c->stats.inner_solves += 1;
+  c->stats.learned_solves += 1;
   c->stats.fallbacks += hs.fallbacks;
+  if (hs.fallbacks > 0) {
+    if (++L->fails >= 2) L->off = true;
+  } else {
+    L->fails = 0;
+  }
   if (hs.nonfinite) return GKB_ENAN;
   if (hs.status == -5) return GKB_EINNER;
   return GKB_OK;
