@@ -71,6 +71,16 @@ extern "C" {
 #define GKB_INNER_LEARNED 2  /* flexible CG, preconditioner = V-cycle + CNN
                                 correction, falling back to MG-PCG */
 
+/* multigrid smoother */
+#define GKB_SMOOTH_JACOBI 0  /* weighted Jacobi on M */
+#define GKB_SMOOTH_HYBRID 1  /* weighted Jacobi on M, each sweep paired with a
+                                weighted-Jacobi sweep on the edge operator
+                                C^T W C mapped back by the discrete curl C
+                                (smooths the divergence-free error that point
+                                Jacobi leaves when eta >> mu); face then edge
+                                before, edge then face after the coarse
+                                correction, so the V-cycle stays symmetric */
+
 typedef struct {
   int dim;       /* 2 or 3 */
   int n[3];      /* cells per axis (n[2] ignored in 2D) */
@@ -92,13 +102,17 @@ typedef struct {
   int maxit;            /* maximum number of GKB steps (zeta values) per sweep */
   double refine_tol;    /* 0: one GKB run (the paper's method).  > 0: repeat
                            GKB on the FP64 saddle residual (defect correction)
-                           until ||res|| <= refine_tol ||[g; r]|| */
+                           until ||res|| <= refine_tol ||[g; r]||; after three
+                           sweeps without a new smallest ||res|| (inner solves
+                           too inexact for the correction to converge) the
+                           solve returns GKB_MAXIT with the best iterate */
   int max_sweeps;       /* cap on defect-correction sweeps */
   int check_every;      /* inner iterations between host convergence checks */
   int use_graphs;       /* capture inner iterations in HIP graphs (1) or not */
   int stencil;          /* 0: LDS-tiled 3D stencil kernel where it applies (3D
                            grids whose +x, +y, +z sides are DIRICHLET), generic
                            face kernel elsewhere; 1: generic face kernel only */
+  int smoother;         /* GKB_SMOOTH_JACOBI or GKB_SMOOTH_HYBRID */
   void *hip_stream;     /* hipStream_t; NULL = null stream */
   size_t max_workspace_bytes; /* 0 = unlimited; else setup fails with
                                  GKB_ENOMEM above this device footprint */
@@ -122,12 +136,14 @@ typedef struct {
   size_t workspace_bytes; /* device memory held by the context */
   int mg_levels;          /* levels actually used */
   double omega[16];       /* Jacobi weight per level */
+  double omega_edge[16];  /* edge-sweep weight per level (hybrid smoother; 0
+                             otherwise) */
 } gkb_stats_t;
 
 typedef struct gkb_ctx gkb_ctx;
 
-/* Fill *opt with defaults: FP64, MG inner, auto levels, V(2,2),
-   inner_tol 1e-10, inner_maxit 10000, maxit 500, refine_tol 0,
+/* Fill *opt with defaults: FP64, MG inner, auto levels, V(2,2), Jacobi
+   smoother, inner_tol 1e-10, inner_maxit 10000, maxit 500, refine_tol 0,
    max_sweeps 10, check_every 8, graphs on, null stream. */
 void gkb_default_options(gkb_options *opt);
 

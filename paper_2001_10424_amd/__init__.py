@@ -45,7 +45,7 @@ class Solver:
     mu: host array of cell viscosities (numpy / CPU tensor) or None (mu = 1).
     eta: augmented-Lagrangian parameter (the paper's nu; 0 = off).
     options: precision ("fp64" | "mixed"), inner ("jacobi" | "mg" | "learned"),
-      mg_levels, nu_pre, nu_post, inner_tol, inner_maxit, maxit, refine_tol,
+      smoother ("jacobi" | "hybrid"), mg_levels, nu_pre, nu_post, inner_tol, inner_maxit, maxit, refine_tol,
       max_sweeps, check_every, use_graphs, max_workspace_bytes.
     """
 
@@ -63,6 +63,8 @@ class Solver:
                 v = {"fp64": _abi.FP64, "mixed": _abi.MIXED}.get(v, v)
             elif k == "inner":
                 v = _abi.INNER.get(v, v)
+            elif k == "smoother":
+                v = _abi.SMOOTHERS.get(v, v)
             if not hasattr(opt, k):
                 raise TypeError(f"unknown option {k}")
             setattr(opt, k, v)
@@ -135,7 +137,8 @@ class Solver:
                     residual=st.residual,
                     seconds_solve=st.seconds_solve, zeta=list(st.zeta[:n]),
                     estimate=list(st.estimate[:n]), workspace_bytes=st.workspace_bytes,
-                    mg_levels=st.mg_levels, omega=list(st.omega[:st.mg_levels]))
+                    mg_levels=st.mg_levels, omega=list(st.omega[:st.mg_levels]),
+                    omega_edge=list(st.omega_edge[:st.mg_levels]))
 
     def apply(self, op, x, precision="fp64"):
         """y = op(x) for op in W, A, AT, M, diag (gkb_apply)."""

@@ -15,6 +15,7 @@ FP64, MIXED = 0, 1
 INNER = {"jacobi": 0, "mg": 1, "learned": 2}
 OPS = {"W": 0, "A": 1, "AT": 2, "M": 3, "diag": 4}
 KERNELS = {"smooth": 0, "apply": 1, "resid": 2}
+SMOOTHERS = {"jacobi": 0, "hybrid": 1}
 
 class Grid(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("h", C.c_double),
@@ -26,7 +27,7 @@ class Options(C.Structure):
                 ("nu_pre", C.c_int), ("nu_post", C.c_int), ("inner_tol", C.c_double),
                 ("inner_maxit", C.c_int), ("maxit", C.c_int), ("refine_tol", C.c_double),
                 ("max_sweeps", C.c_int), ("check_every", C.c_int), ("use_graphs", C.c_int),
-                ("stencil", C.c_int),
+                ("stencil", C.c_int), ("smoother", C.c_int),
                 ("hip_stream", C.c_void_p), ("max_workspace_bytes", C.c_size_t)]
 
 
@@ -37,7 +38,8 @@ class Stats(C.Structure):
                 ("error_estimate", C.c_double), ("seconds_solve", C.c_double),
                 ("history_len", C.c_int), ("zeta", C.c_double * 512),
                 ("estimate", C.c_double * 512), ("workspace_bytes", C.c_size_t),
-                ("mg_levels", C.c_int), ("omega", C.c_double * 16)]
+                ("mg_levels", C.c_int), ("omega", C.c_double * 16),
+                ("omega_edge", C.c_double * 16)]
 
 
 _lib = None

@@ -29,6 +29,7 @@
 #include "cnn.hpp"
 #include "learned.hpp"
 #include "tile3d.hpp"
+#include "hybrid.hpp"
 
 using namespace gkb;
 
@@ -156,6 +157,9 @@ struct Level {
   T *b = nullptr, *x = nullptr, *t = nullptr, *rb = nullptr;
   double omega = 0.8;
   FaceLaunch fl;
+  // hybrid smoother: edge potential and 1/diag(C^T W C) (nullptr: Jacobi only)
+  T *psi = nullptr, *edinv = nullptr;
+  double omega_e = 0.0;
 };
 
 template <typename T>
@@ -186,6 +190,8 @@ struct gkb_ctx {
   std::vector<Coef<double>> coef64;
   std::vector<Coef<float>> coef32;
   std::vector<double> omega;
+  std::vector<double> omega_e;               // edge-sweep weights (hybrid)
+  std::vector<std::vector<double>> edinv_h;  // 1/diag(C^T W C) per level (hybrid)
   Op<double> op64;  // finest FP64 M
   Op<float> op32;
   double* Minv = nullptr;
@@ -195,6 +201,7 @@ struct gkb_ctx {
   // GKB vectors
   double *ghat = nullptr, *w0 = nullptr, *u = nullptr, *v = nullptr, *Mv = nullptr, *s = nullptr,
          *y = nullptr, *f = nullptr, *rw = nullptr, *dw = nullptr;
+  double *wbest = nullptr, *pbest = nullptr;  // best defect-correction iterate
   double *b = nullptr, *q = nullptr, *d = nullptr, *t = nullptr, *rr = nullptr, *dp = nullptr;
   double* part[kSlots] = {nullptr};
   int maxparts = 0;
@@ -262,6 +269,21 @@ int host_sum(gkb_ctx* c, const double* partial, int n, double* out) {
 
 // ---------------------------------------------------------- multigrid
 
+// x += C omega_e D_e^-1 C^T (b - M x): the edge half of the hybrid smoother
+template <typename T>
+void edge_step(gkb_ctx* c, Level<T>& L, const T* b, T* x, const PcgState* st) {
+  hipStream_t s = c->cs;
+  face_op<T, kResid>(c, L.op, L.fl, x, b, L.rb, T(0), nullptr, st);
+  const dim3 cg = cell_grid(L.g);
+  if (L.g.dim == 2) {
+    k_edge_ct<T, 2><<<cg, kBlock, 0, s>>>(L.g, L.rb, L.edinv, T(L.omega_e), L.psi, st);
+    k_curl_add<T, 2><<<cg, kBlock, 0, s>>>(L.g, L.psi, x, st);
+  } else {
+    k_edge_ct<T, 3><<<cg, kBlock, 0, s>>>(L.g, L.rb, L.edinv, T(L.omega_e), L.psi, st);
+    k_curl_add<T, 3><<<cg, kBlock, 0, s>>>(L.g, L.psi, x, st);
+  }
+}
+
 template <typename T>
 void vcycle(gkb_ctx* c, Inner<T>& in, int l, const T* b, T* x, double* dot_partial,
             const PcgState* st) {
@@ -277,6 +299,7 @@ void vcycle(gkb_ctx* c, Inner<T>& in, int l, const T* b, T* x, double* dot_parti
   }
   const int n1 = c->opt.nu_pre, n2 = c->opt.nu_post, tot = n1 + n2;
   const T om = T(L.omega);
+  const bool hybrid = L.psi != nullptr;
   // sweep k writes x when (tot - k) is even, else t
   auto dst = [&](int k) { return ((tot - k) % 2 == 0) ? x : L.t; };
   const T* cur = nullptr;
@@ -285,11 +308,13 @@ void vcycle(gkb_ctx* c, Inner<T>& in, int l, const T* b, T* x, double* dot_parti
     ++k;
     T* o = dst(k);
     face_op<T, kJacobi0>(c, L.op, L.fl, nullptr, b, o, om, nullptr, st);
+    if (hybrid) edge_step<T>(c, L, b, o, st);
     cur = o;
     for (int i = 1; i < n1; ++i) {
       ++k;
       T* o2 = dst(k);
       face_op<T, kJacobi>(c, L.op, L.fl, cur, b, o2, om, nullptr, st);
+      if (hybrid) edge_step<T>(c, L, b, o2, st);
       cur = o2;
     }
   }
@@ -318,6 +343,7 @@ void vcycle(gkb_ctx* c, Inner<T>& in, int l, const T* b, T* x, double* dot_parti
     ++k;
     T* o = (cur == x) ? L.t : x;
     const bool last = (i == n2 - 1);
+    if (hybrid) edge_step<T>(c, L, b, const_cast<T*>(cur), st);
     if (last && dot_partial)
       face_op<T, kJacobiDot>(c, L.op, L.fl, cur, b, o, om, dot_partial, st);
     else
@@ -678,6 +704,89 @@ bool spd_inverse(std::vector<double>& A, int n) {
   return true;
 }
 
+// Hybrid smoother set-up on every level but the coarsest (FP64):
+// diag(C^T W C) by probing (27 (3D) or 9 (2D) edge classes per component,
+// see k_edge_probe), its inverse, and the edge-sweep weight
+// omega_e = 1.5 / (1.05 lambda) from 30 power steps on D_e^-1 C^T W C
+// (lambda underestimates the top eigenvalue slightly, hence 1.05; 1.5 / lambda
+// was the fastest of 0.7, 1.0, 1.5, 1.8 on the 128^3 lid-driven problem).
+template <int DIM>
+int edge_setup_level(gkb_ctx* c, int l, double* psi, double* t, double* dg, double* cf,
+                     double* y) {
+  const Grid& g = c->grids[l];
+  hipStream_t s = c->cs;
+  const Op<double> opW = make_op<double>(g, 0.0, c->coef64[l], c->varmu);
+  const FaceLaunch fl = face_launch(g, 4, c->opt.stencil);
+  const long ne = (long)edge_comps<DIM>() * g.n_cells;
+  const int m = g.m_full;
+  const dim3 cg = cell_grid(g);
+  const int eb = (int)std::min<long>(4096, (ne + kBlock - 1) / kBlock);
+  k_fill<double><<<vec_blocks((int)ne), kBlock, 0, s>>>((int)ne, 0.0, dg);
+  for (int a = 0; a < edge_comps<DIM>(); ++a)
+    for (int cz = 0; cz < (DIM == 3 ? 3 : 1); ++cz)
+      for (int cy = 0; cy < 3; ++cy)
+        for (int cx = 0; cx < 3; ++cx) {
+          k_edge_probe<DIM><<<cg, kBlock, 0, s>>>(g, a, cx, cy, cz, psi);
+          k_fill<double><<<vec_blocks(m), kBlock, 0, s>>>(m, 0.0, cf);
+          k_curl_add<double, DIM><<<cg, kBlock, 0, s>>>(g, psi, cf, nullptr);
+          face_op<double, kApply>(c, opW, fl, cf, nullptr, y, 0.0, nullptr, nullptr);
+          k_edge_ct<double, DIM><<<cg, kBlock, 0, s>>>(g, y, nullptr, 1.0, t, nullptr);
+          k_edge_collect<<<eb, kBlock, 0, s>>>(ne, psi, t, dg);
+        }
+  std::vector<double> dh(ne);
+  HIPCK(hipMemcpyAsync(dh.data(), dg, ne * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  for (auto& v : dh) v = v > 0.0 ? 1.0 / v : 0.0;
+  HIPCK(hipMemcpy(dg, dh.data(), ne * sizeof(double), hipMemcpyHostToDevice));
+  // power iteration from D_e^-1 C^T (seeded random faces)
+  std::vector<double> f0(m);
+  unsigned sd = 54321u;
+  for (auto& v : f0) {
+    sd = sd * 1664525u + 1013904223u;
+    v = (sd >> 8) * (1.0 / 16777216.0) - 0.5;
+  }
+  HIPCK(hipMemcpy(cf, f0.data(), m * sizeof(double), hipMemcpyHostToDevice));
+  k_edge_ct<double, DIM><<<cg, kBlock, 0, s>>>(g, cf, dg, 1.0, psi, nullptr);
+  double lam = 1.0;
+  for (int it = 0; it < 30; ++it) {
+    k_fill<double><<<vec_blocks(m), kBlock, 0, s>>>(m, 0.0, cf);
+    k_curl_add<double, DIM><<<cg, kBlock, 0, s>>>(g, psi, cf, nullptr);
+    face_op<double, kApply>(c, opW, fl, cf, nullptr, y, 0.0, nullptr, nullptr);
+    k_edge_ct<double, DIM><<<cg, kBlock, 0, s>>>(g, y, dg, 1.0, t, nullptr);
+    double tt = 0.0, xx = 0.0;
+    k_dot<double><<<vec_blocks((int)ne), kBlock, 0, s>>>((int)ne, t, t, c->part[0]);
+    CK(host_sum(c, c->part[0], vec_blocks((int)ne), &tt));
+    k_dot<double><<<vec_blocks((int)ne), kBlock, 0, s>>>((int)ne, psi, psi, c->part[1]);
+    CK(host_sum(c, c->part[1], vec_blocks((int)ne), &xx));
+    if (!(tt > 0.0) || !(xx > 0.0)) break;
+    lam = std::sqrt(tt / xx);
+    k_axpby<<<vec_blocks((int)ne), kBlock, 0, s>>>((int)ne, 1.0 / std::sqrt(tt), t, 0.0, psi);
+  }
+  c->omega_e[l] = 1.5 / (1.05 * lam);
+  c->edinv_h[l] = std::move(dh);
+  return GKB_OK;
+}
+
+int edge_setup(gkb_ctx* c) {
+  const int L = c->L;
+  c->omega_e.assign(L, 0.0);
+  c->edinv_h.assign(L, std::vector<double>());
+  if (L < 2) return GKB_OK;
+  const Grid& g0 = c->grids[0];
+  const long ne = (long)(g0.dim == 3 ? 3 : 1) * g0.n_cells;
+  double *psi, *t, *dg, *cf, *y;
+  CK(c->mem.arr(&psi, ne));
+  CK(c->mem.arr(&t, ne));
+  CK(c->mem.arr(&dg, ne));
+  CK(c->mem.arr(&cf, g0.m_full));
+  CK(c->mem.arr(&y, g0.m_full));
+  for (int l = 0; l < L - 1; ++l) {
+    if (g0.dim == 2) CK(edge_setup_level<2>(c, l, psi, t, dg, cf, y));
+    else CK(edge_setup_level<3>(c, l, psi, t, dg, cf, y));
+  }
+  return GKB_OK;
+}
+
 template <typename T>
 int build_inner(gkb_ctx* c, Inner<T>& in, const std::vector<Coef<T>>& coef) {
   const int L = c->L;
@@ -695,6 +804,12 @@ int build_inner(gkb_ctx* c, Inner<T>& in, const std::vector<Coef<T>>& coef) {
     }
     CK(c->mem.arr(&lv.t, m));
     CK(c->mem.arr(&lv.rb, m));
+    if (l < L - 1 && l < (int)c->edinv_h.size() && !c->edinv_h[l].empty()) {
+      const std::vector<double>& dh = c->edinv_h[l];
+      CK(c->mem.arr(&lv.psi, dh.size()));
+      CK(upload<T>(c, dh, &lv.edinv));
+      lv.omega_e = c->omega_e[l];
+    }
   }
   const int m = c->g.m_full;
   CK(c->mem.arr(&in.x, m));
@@ -823,6 +938,10 @@ int setup_impl(gkb_ctx* c, const gkb_grid* grid, const double* visc, double eta,
   for (auto pp : fv) CK(c->mem.arr(pp, m));
   double** cv[] = {&c->b, &c->q, &c->d, &c->t, &c->rr, &c->dp};
   for (auto pp : cv) CK(c->mem.arr(pp, nc));
+  if (opt->refine_tol > 0.0) {
+    CK(c->mem.arr(&c->wbest, m));
+    CK(c->mem.arr(&c->pbest, nc));
+  }
   // Jacobi weights by power iteration on D^-1 M_l (FP64), omega = 1.6 / (1.05 lambda)
   c->omega.assign(L, 0.8);
   for (int l = 0; l < L - (L > 1 ? 1 : 0); ++l) {
@@ -852,6 +971,7 @@ int setup_impl(gkb_ctx* c, const gkb_grid* grid, const double* visc, double eta,
     }
     c->omega[l] = 1.6 / (1.05 * lam);
   }
+  if (opt->smoother == GKB_SMOOTH_HYBRID && opt->inner != GKB_INNER_JACOBI) CK(edge_setup(c));
   // coarsest level: dense FP64 inverse of M on the unknown faces
   if (opt->inner != GKB_INNER_JACOBI) {
     const Grid& g = c->grids[L - 1];
@@ -922,6 +1042,7 @@ int validate(const gkb_grid* g, double eta, const gkb_options* o) {
   if (o->nu_pre < 0 || o->nu_post < 0 || o->nu_pre + o->nu_post < 1) return GKB_EINVAL;
   if (o->inner_maxit < 1 || o->maxit < 1 || o->max_sweeps < 1) return GKB_EINVAL;
   if (o->check_every < 1 || o->stencil < 0 || o->stencil > 1) return GKB_EINVAL;
+  if (o->smoother != GKB_SMOOTH_JACOBI && o->smoother != GKB_SMOOTH_HYBRID) return GKB_EINVAL;
   return GKB_OK;
 }
 
@@ -946,6 +1067,7 @@ void gkb_default_options(gkb_options* o) {
   o->check_every = 8;
   o->use_graphs = 1;
   o->stencil = 0;
+  o->smoother = GKB_SMOOTH_JACOBI;
   o->hip_stream = nullptr;
   o->max_workspace_bytes = 0;
 }
@@ -1000,6 +1122,16 @@ int gkb_solve(gkb_ctx* c, const double* g, const double* r, double tol, int dela
     k_fill<double><<<vec_blocks(m), kBlock, 0, c->cs>>>(m, 0.0, w);
     k_fill<double><<<vec_blocks(nc), kBlock, 0, c->cs>>>(nc, 0.0, p);
     double norms[4];
+    // best iterate so far: a sweep may raise the residual before later ones
+    // converge, but three sweeps without a new best (or growth by 1e3) mean
+    // the inner solves are too inexact for the correction to converge
+    double best = HUGE_VAL;
+    int since_best = 0;
+    auto restore_best = [&]() {
+      k_cast<double, double><<<vec_blocks(m), kBlock, 0, c->cs>>>(m, c->wbest, w);
+      k_cast<double, double><<<vec_blocks(nc), kBlock, 0, c->cs>>>(nc, c->pbest, p);
+      c->stats.residual = best;
+    };
     rc = GKB_MAXIT;
     for (int sw = 0; sw <= c->opt.max_sweeps; ++sw) {
       int r2 = residual_impl(c, g, r, w, p, c->rw, c->rr, norms);
@@ -1007,14 +1139,26 @@ int gkb_solve(gkb_ctx* c, const double* g, const double* r, double tol, int dela
       const double rel = norms[3] > 0 ? norms[0] / norms[3] : 0.0;
       c->stats.residual = rel;
       if (!std::isfinite(rel)) {
+        if (sw > 0) restore_best();
         rc = GKB_ENAN;
         break;
+      }
+      if (rel < best) {
+        best = rel;
+        since_best = 0;
+        k_cast<double, double><<<vec_blocks(m), kBlock, 0, c->cs>>>(m, w, c->wbest);
+        k_cast<double, double><<<vec_blocks(nc), kBlock, 0, c->cs>>>(nc, p, c->pbest);
+      } else {
+        ++since_best;
       }
       if (rel <= c->opt.refine_tol) {
         rc = GKB_OK;
         break;
       }
-      if (sw == c->opt.max_sweeps) break;
+      if (since_best >= 3 || rel > 1e3 * best || sw == c->opt.max_sweeps) {
+        if (rel > best) restore_best();
+        break;
+      }
       int r3 = gkb_run(c, c->rw, c->rr, tol, delay, c->dw, c->dp, &K, &est);
       c->stats.sweeps += 1;
       if (r3 < 0) {
@@ -1039,6 +1183,7 @@ int gkb_stats(const gkb_ctx* c, gkb_stats_t* out) {
   out->workspace_bytes = c->mem.bytes;
   out->mg_levels = c->L;
   for (int l = 0; l < c->L && l < 16; ++l) out->omega[l] = c->omega[l];
+  for (int l = 0; l < (int)c->omega_e.size() && l < 16; ++l) out->omega_edge[l] = c->omega_e[l];
   return GKB_OK;
 }
 

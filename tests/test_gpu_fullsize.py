@@ -33,6 +33,10 @@ BENCH_MODES = {
     "fp64_mg": dict(precision="fp64", inner="mg", inner_tol=1e-3, tol=1e-2, delay=2),
     "mixed_mg": dict(precision="mixed", inner="mg", inner_tol=1e-3, tol=1e-2, delay=2),
     "fp64_gkb1": dict(precision="fp64", inner="mg", inner_tol=1e-10, tol=1e-9, delay=5),
+    "fp64_mg_hybrid": dict(precision="fp64", inner="mg", inner_tol=3e-4, tol=3e-3, delay=2,
+                           smoother="hybrid", nu_pre=1, nu_post=1),
+    "mixed_mg_hybrid": dict(precision="mixed", inner="mg", inner_tol=3e-4, tol=3e-3, delay=2,
+                            smoother="hybrid", nu_pre=1, nu_post=1),
 }
 
 
@@ -40,15 +44,17 @@ def _solve(pr, mode):
     gk = _gk()
     m = dict(BENCH_MODES[mode])
     tol, delay = m.pop("tol"), m.pop("delay")
-    s = gk.Solver(pr.grid, pr.mu, pr.eta, nu_pre=2, nu_post=2, inner_maxit=5000, maxit=200,
-                  refine_tol=1e-8, max_sweeps=12, check_every=8, **m)
+    kw = dict(nu_pre=2, nu_post=2, inner_maxit=5000, maxit=200, refine_tol=1e-8, max_sweeps=12,
+              check_every=8)
+    kw.update(m)
+    s = gk.Solver(pr.grid, pr.mu, pr.eta, **kw)
     w, p, info = s.solve(_dev(pr.g), _dev(pr.r), tol=tol, delay=delay)
     out = w.cpu().numpy(), p.cpu().numpy(), info
     s.close()
     return out
 
 
-@pytest.mark.parametrize("mode", ["mixed_mg", "fp64_mg", "fp64_gkb1"])
+@pytest.mark.parametrize("mode", list(BENCH_MODES))
 def test_stokes3d_128_lid_bench_config(mode):
     """The benchmarked workload: FP64 residual <= 1e-8 by the oracle."""
     _say("stokes3d_128_lid", mode)

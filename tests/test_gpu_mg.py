@@ -45,11 +45,12 @@ def _mu(g, on):
     return np.exp(np.random.default_rng(5).standard_normal(g.n_cells)) if on else None
 
 
+@pytest.mark.parametrize("smoother", ["jacobi", "hybrid"])
 @pytest.mark.parametrize("name,grid,eta,varmu", MG_CASES, ids=[c[0] for c in MG_CASES])
-def test_vcycle_symmetric_positive(name, grid, eta, varmu):
-    _say("vcycle sym", name)
+def test_vcycle_symmetric_positive(name, grid, eta, varmu, smoother):
+    _say("vcycle sym", name, smoother)
     gk = _gk()
-    s = gk.Solver(grid, _mu(grid, varmu), eta, inner="mg")
+    s = gk.Solver(grid, _mu(grid, varmu), eta, inner="mg", smoother=smoother)
     x = _dev(P.random_vector(grid, 1))
     y = _dev(P.random_vector(grid, 2))
     Vx = s.precondition(x)
@@ -64,15 +65,16 @@ def test_vcycle_symmetric_positive(name, grid, eta, varmu):
     s.close()
 
 
+@pytest.mark.parametrize("smoother", ["jacobi", "hybrid"])
 @pytest.mark.parametrize("name,grid,eta,varmu", MG_CASES[:2], ids=[c[0] for c in MG_CASES[:2]])
-def test_tiled_matches_generic(name, grid, eta, varmu):
+def test_tiled_matches_generic(name, grid, eta, varmu, smoother):
     """The LDS-tiled 3D kernel and the generic face kernel compute the same
     operator, V-cycle (every smoother / residual mode) and inner solve."""
-    _say("tiled vs generic", name)
+    _say("tiled vs generic", name, smoother)
     gk = _gk()
     mu = _mu(grid, varmu)
-    s0 = gk.Solver(grid, mu, eta, inner="mg", stencil=0)
-    s1 = gk.Solver(grid, mu, eta, inner="mg", stencil=1)
+    s0 = gk.Solver(grid, mu, eta, inner="mg", stencil=0, smoother=smoother)
+    s1 = gk.Solver(grid, mu, eta, inner="mg", stencil=1, smoother=smoother)
     x = _dev(np.random.default_rng(3).standard_normal(grid.m_full))
     for op in ("M", "W"):
         a, b = s0.apply(op, x).cpu().numpy(), s1.apply(op, x).cpu().numpy()
@@ -106,12 +108,13 @@ def test_vcycle_laplacian_convergence_factor():
     assert max(its) <= 20 and its[-1] <= its[0] + 4, its
 
 
+@pytest.mark.parametrize("smoother", ["jacobi", "hybrid"])
 @pytest.mark.parametrize("name,grid,eta,varmu", MG_CASES, ids=[c[0] for c in MG_CASES])
-def test_mg_pcg_solution_matches_oracle(name, grid, eta, varmu):
-    _say("mg-pcg vs oracle", name)
+def test_mg_pcg_solution_matches_oracle(name, grid, eta, varmu, smoother):
+    _say("mg-pcg vs oracle", name, smoother)
     gk = _gk()
     mu = _mu(grid, varmu)
-    s = gk.Solver(grid, mu, eta, inner="mg", inner_maxit=20000)
+    s = gk.Solver(grid, mu, eta, inner="mg", inner_maxit=20000, smoother=smoother)
     f = P.random_vector(grid, 6)
     x, it = s.inner_solve(_dev(f), 1e-12)
     ref, st, _ = oracle.pcg(grid, f, eta, mu, tol=1e-13, maxit=10 ** 6)
@@ -123,14 +126,16 @@ def test_mg_pcg_solution_matches_oracle(name, grid, eta, varmu):
     s.close()
 
 
+@pytest.mark.parametrize("smoother", ["jacobi", "hybrid"])
 @pytest.mark.parametrize("dim,n,varmu", [(3, 16, False), (2, 32, True)])
-def test_mg_gkb_matches_oracle(dim, n, varmu):
+def test_mg_gkb_matches_oracle(dim, n, varmu, smoother):
     """GKB with the MG-PCG inner solve against the oracle (Jacobi-PCG inner):
     both inner solves converged to 1e-13, so the GKB iterates agree."""
-    _say("mg-gkb vs oracle", dim, n, varmu)
+    _say("mg-gkb vs oracle", dim, n, varmu, smoother)
     gk = _gk()
     pr = P.stokes_problem(dim, n, seed=3, eta=1e2, lid=True, mu_seed=(7 if varmu else None))
-    s = gk.Solver(pr.grid, pr.mu, pr.eta, inner="mg", inner_tol=1e-13, inner_maxit=50000)
+    s = gk.Solver(pr.grid, pr.mu, pr.eta, inner="mg", inner_tol=1e-13, inner_maxit=50000,
+                  smoother=smoother)
     w, p, info = s.solve(_dev(pr.g), _dev(pr.r), tol=1e-9, delay=5)
     ref = oracle.gkb_solve(pr.grid, pr.g, pr.r, pr.eta, mu=pr.mu, tol=1e-9, delay=5, maxit=300,
                            inner_tol=1e-13, inner_maxit=10 ** 6)
@@ -140,17 +145,20 @@ def test_mg_gkb_matches_oracle(dim, n, varmu):
     s.close()
 
 
-@pytest.mark.parametrize("dim,n,varmu,eta", [(3, 32, False, 1e3), (2, 64, True, 1e3),
-                                             (3, 16, True, 1e2)])
-def test_mixed_precision_residual(dim, n, varmu, eta):
+@pytest.mark.parametrize("dim,n,varmu,eta,smoother", [(3, 32, False, 1e3, "jacobi"),
+                                                      (2, 64, True, 1e3, "jacobi"),
+                                                      (3, 16, True, 1e2, "jacobi"),
+                                                      (3, 32, False, 1e3, "hybrid"),
+                                                      (2, 64, True, 1e3, "hybrid")])
+def test_mixed_precision_residual(dim, n, varmu, eta, smoother):
     """FP32 inner MG-PCG inside FP64 GKB sweeps with FP64 defect correction:
     the FP64 saddle residual, recomputed by the oracle, is <= 1e-8; the
     difference to the oracle's FP64 solution is reported against it."""
-    _say("mixed", dim, n, varmu, eta)
+    _say("mixed", dim, n, varmu, eta, smoother)
     gk = _gk()
     pr = P.stokes_problem(dim, n, seed=4, eta=eta, lid=(dim == 3), mu_seed=(8 if varmu else None))
     s = gk.Solver(pr.grid, pr.mu, pr.eta, precision="mixed", inner="mg", inner_tol=1e-5,
-                  refine_tol=1e-8, max_sweeps=12, maxit=200)
+                  refine_tol=1e-8, max_sweeps=12, maxit=200, smoother=smoother)
     w, p, info = s.solve(_dev(pr.g), _dev(pr.r), tol=1e-4, delay=5)
     wn, pn = w.cpu().numpy(), p.cpu().numpy()
     _, _, nr = oracle.saddle_residual(pr.grid, pr.g, pr.r, wn, pn, mu=pr.mu)
@@ -169,4 +177,48 @@ def test_fp64_mg_refinement_residual():
     w, p, info = s.solve(_dev(pr.g), _dev(pr.r), tol=1e-9, delay=5)
     _, _, nr = oracle.saddle_residual(pr.grid, pr.g, pr.r, w.cpu().numpy(), p.cpu().numpy())
     assert nr[0] <= 1e-8 * nr[3]
+    s.close()
+
+
+@pytest.mark.parametrize("dim,n,varmu", [(3, 32, False), (2, 128, False), (3, 24, True)])
+def test_hybrid_smoother_robust_in_eta(dim, n, varmu):
+    """At eta = 1e3 point-Jacobi multigrid leaves the divergence-free error of
+    every level unsmoothed; the edge sweeps of the hybrid smoother remove it:
+    at most a third of the MG-PCG iterations, edge weights on every level but
+    the dense coarsest one."""
+    _say("hybrid robustness", dim, n, varmu)
+    gk = _gk()
+    g = P.Grid(dim, (n, n, n if dim == 3 else 1), 1 / n, (D,) * 6, 0)
+    mu = _mu(g, varmu)
+    f = _dev(P.random_vector(g, 8))
+    its = {}
+    for sm in ("jacobi", "hybrid"):
+        s = gk.Solver(g, mu, 1e3, inner="mg", smoother=sm, inner_maxit=20000)
+        x, its[sm] = s.inner_solve(f, 1e-6)
+        res = f.cpu().numpy() - oracle.apply_M(g, x.cpu().numpy(), 1e3, mu)
+        assert np.linalg.norm(res) <= 1.01e-6 * np.linalg.norm(f.cpu().numpy())
+        om = s.stats()["omega_edge"]
+        if sm == "hybrid":
+            assert all(v > 0 for v in om[:-1]) and om[-1] == 0.0, om
+        else:
+            assert all(v == 0.0 for v in om)
+        s.close()
+    assert 3 * its["hybrid"] <= its["jacobi"], its
+
+
+def test_refinement_stops_when_a_sweep_does_not_reduce_the_residual():
+    """Defect correction with inner solves far too loose for the sweep to
+    converge: the solve ends with GKB_MAXIT (or GKB_OK), never above the
+    initial residual, and the reported residual is that of the returned
+    iterate."""
+    _say("refinement guard")
+    gk = _gk()
+    pr = P.stokes_problem(3, 32, seed=0, eta=1e3, lid=True)
+    s = gk.Solver(pr.grid, None, pr.eta, precision="mixed", inner="mg", inner_tol=0.3,
+                  refine_tol=1e-12, max_sweeps=30, maxit=50)
+    w, p, info = s.solve(_dev(pr.g), _dev(pr.r), tol=0.3, delay=1)
+    assert info["status"] in (0, 1)
+    _, _, nr = oracle.saddle_residual(pr.grid, pr.g, pr.r, w.cpu().numpy(), p.cpu().numpy())
+    assert nr[0] <= nr[3]
+    assert abs(info["residual"] - nr[0] / nr[3]) <= 1e-6 * nr[0] / nr[3]
     s.close()
