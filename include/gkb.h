@@ -138,6 +138,11 @@ typedef struct {
   double omega[16];       /* Jacobi weight per level */
   double omega_edge[16];  /* edge-sweep weight per level (hybrid smoother; 0
                              otherwise) */
+  double learned_gain;    /* mean over the network applications of the last
+                             gkb_solve of the error energy removed by the
+                             network step relative to the V-cycle step,
+                             (c.rt)^2 / (c.Mc) / (r.V(r)); -1 if none.  Below
+                             0.05 an inner solve falls back to MG-PCG */
 } gkb_stats_t;
 
 typedef struct gkb_ctx gkb_ctx;

@@ -24,7 +24,10 @@
  * memory.
  *
  * All pointers are device pointers unless marked host.  Calls are
- * synchronous.  Errors as in gkb.h (GKB_EINVAL, GKB_ENOMEM, GKB_EHIP).
+ * synchronous: the calls that read device buffers (forward, backward, train,
+ * eval) first wait for all work already submitted to the device, so buffers
+ * written on any stream are complete, and return when their own work is
+ * done.  Errors as in gkb.h (GKB_EINVAL, GKB_ENOMEM, GKB_EHIP).
  */
 #ifndef GKB_CNN_H
 #define GKB_CNN_H

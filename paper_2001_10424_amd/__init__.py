@@ -138,7 +138,8 @@ class Solver:
                     seconds_solve=st.seconds_solve, zeta=list(st.zeta[:n]),
                     estimate=list(st.estimate[:n]), workspace_bytes=st.workspace_bytes,
                     mg_levels=st.mg_levels, omega=list(st.omega[:st.mg_levels]),
-                    omega_edge=list(st.omega_edge[:st.mg_levels]))
+                    omega_edge=list(st.omega_edge[:st.mg_levels]),
+                    learned_gain=st.learned_gain)
 
     def apply(self, op, x, precision="fp64"):
         """y = op(x) for op in W, A, AT, M, diag (gkb_apply)."""

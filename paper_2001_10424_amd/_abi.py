@@ -39,7 +39,7 @@ class Stats(C.Structure):
                 ("history_len", C.c_int), ("zeta", C.c_double * 512),
                 ("estimate", C.c_double * 512), ("workspace_bytes", C.c_size_t),
                 ("mg_levels", C.c_int), ("omega", C.c_double * 16),
-                ("omega_edge", C.c_double * 16)]
+                ("omega_edge", C.c_double * 16), ("learned_gain", C.c_double)]
 
 
 _lib = None

@@ -407,6 +407,13 @@ namespace {
     }                                                                            \
   } while (0)
 
+// Host <-> device copy ordered on the network's (non-blocking) stream and
+// complete on return
+hipError_t cnn_copy(gkb_cnn* n, void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, n->s);
+  return e != hipSuccess ? e : hipStreamSynchronize(n->s);
+}
+
 int cnn_grid(long n) { return (int)std::max<long>(1, std::min<long>((n + 255) / 256, 8192)); }
 
 int cnn_prepare_weights(gkb_cnn* n) {
@@ -549,7 +556,7 @@ int gkb_cnn_create(int dim, int n_layers, const int* channels, unsigned seed, gk
   float** fp[] = {&n->params, &n->grad, &n->m, &n->v};
   for (auto p : fp) {
     if (hipMalloc(p, n->np * sizeof(float)) != hipSuccess) return fail(GKB_ENOMEM);
-    if (hipMemset(*p, 0, n->np * sizeof(float)) != hipSuccess) return fail(GKB_EHIP);
+    if (hipMemsetAsync(*p, 0, n->np * sizeof(float), n->s) != hipSuccess) return fail(GKB_EHIP);
   }
   if (hipMalloc(&n->wf, (size_t)n_layers * n->taps * 256 * 2) != hipSuccess ||
       hipMalloc(&n->wd, (size_t)n_layers * n->taps * 256 * 2) != hipSuccess ||
@@ -569,7 +576,7 @@ int gkb_cnn_create(int dim, int n_layers, const int* channels, unsigned seed, gk
       h[n->off[l] + e] = float((2.0 * u - 1.0) * lim);
     }
   }
-  if (hipMemcpy(n->params, h.data(), n->np * 4, hipMemcpyHostToDevice) != hipSuccess)
+  if (cnn_copy(n, n->params, h.data(), n->np * 4, hipMemcpyHostToDevice) != hipSuccess)
     return fail(GKB_EHIP);
   *out = n;
   return GKB_OK;
@@ -593,18 +600,20 @@ long gkb_cnn_param_count(const gkb_cnn* n) { return n ? n->np : -1; }
 
 int gkb_cnn_set_params(gkb_cnn* n, const float* hp) {
   if (!n || !hp) return GKB_EINVAL;
-  CNNCK(hipMemcpy(n->params, hp, n->np * 4, hipMemcpyHostToDevice));
+  CNNCK(cnn_copy(n, n->params, hp, n->np * 4, hipMemcpyHostToDevice));
   n->weights_dirty = true;
   return GKB_OK;
 }
 
 int gkb_cnn_get_params(const gkb_cnn* n, float* hp) {
   if (!n || !hp) return GKB_EINVAL;
-  CNNCK(hipMemcpy(hp, n->params, n->np * 4, hipMemcpyDeviceToHost));
+  CNNCK(cnn_copy(const_cast<gkb_cnn*>(n), hp, n->params, n->np * 4, hipMemcpyDeviceToHost));
   return GKB_OK;
 }
 
 int gkb_cnn_forward(gkb_cnn* n, int nx, int ny, int nz, int batch, const float* x, float* y) {
+  // inputs may come from any stream: wait for all submitted device work
+  CNNCK(hipDeviceSynchronize());
   if (!n || !x || !y || nx < 1 || ny < 1 || nz < 1 || batch < 1 || (n->dim == 2 && nz != 1))
     return GKB_EINVAL;
   gkb::CnnGeom g{nx, ny, nz, batch, (long)nx * ny * nz * batch};
@@ -620,6 +629,8 @@ int gkb_cnn_forward(gkb_cnn* n, int nx, int ny, int nz, int batch, const float* 
 
 int gkb_cnn_backward(gkb_cnn* n, int nx, int ny, int nz, int batch, const float* x,
                      const float* dy, float* dx, float* grad_host) {
+  // inputs may come from any stream: wait for all submitted device work
+  CNNCK(hipDeviceSynchronize());
   if (!n || !x || !dy || nx < 1 || ny < 1 || nz < 1 || batch < 1 || (n->dim == 2 && nz != 1))
     return GKB_EINVAL;
   gkb::CnnGeom g{nx, ny, nz, batch, (long)nx * ny * nz * batch};
@@ -642,7 +653,7 @@ int gkb_cnn_backward(gkb_cnn* n, int nx, int ny, int nz, int batch, const float*
 int gkb_cnn_adam_step(gkb_cnn* n, const float* grad_host, double lr, double b1, double b2,
                       double eps) {
   if (!n) return GKB_EINVAL;
-  if (grad_host) CNNCK(hipMemcpy(n->grad, grad_host, n->np * 4, hipMemcpyHostToDevice));
+  if (grad_host) CNNCK(cnn_copy(n, n->grad, grad_host, n->np * 4, hipMemcpyHostToDevice));
   int rc = cnn_adam(n, lr, b1, b2, eps);
   if (rc) return rc;
   CNNCK(hipStreamSynchronize(n->s));
@@ -652,6 +663,8 @@ int gkb_cnn_adam_step(gkb_cnn* n, const float* grad_host, double lr, double b1, 
 int gkb_cnn_train(gkb_cnn* n, const float* inputs, const float* targets, int n_pairs, int nx,
                   int ny, int nz, int crop, int batch, int steps, double lr, unsigned seed,
                   float* loss_host) {
+  // inputs may come from any stream: wait for all submitted device work
+  CNNCK(hipDeviceSynchronize());
   if (!n || !inputs || !targets || n_pairs < 1 || batch < 1 || batch > 1024 || steps < 0 ||
       crop < 3 || crop > nx || crop > ny || (n->dim == 3 && crop > nz) || (n->dim == 2 && nz != 1))
     return GKB_EINVAL;
@@ -713,6 +726,8 @@ int gkb_cnn_train(gkb_cnn* n, const float* inputs, const float* targets, int n_p
 
 int gkb_cnn_eval(gkb_cnn* n, const float* inputs, const float* targets, int n_pairs, int nx,
                  int ny, int nz, double* loss) {
+  // inputs may come from any stream: wait for all submitted device work
+  CNNCK(hipDeviceSynchronize());
   if (!n || !inputs || !targets || !loss || n_pairs < 1 || (n->dim == 2 && nz != 1))
     return GKB_EINVAL;
   const int cin = n->ch[0], cout = n->ch[n->L];
@@ -744,9 +759,10 @@ int gkb_cnn_eval(gkb_cnn* n, const float* inputs, const float* targets, int n_pa
 int gkb_cnn_save(const gkb_cnn* n, const char* path) {
   if (!n || !path) return GKB_EINVAL;
   std::vector<float> p(n->np), m(n->np), v(n->np);
-  CNNCK(hipMemcpy(p.data(), n->params, n->np * 4, hipMemcpyDeviceToHost));
-  CNNCK(hipMemcpy(m.data(), n->m, n->np * 4, hipMemcpyDeviceToHost));
-  CNNCK(hipMemcpy(v.data(), n->v, n->np * 4, hipMemcpyDeviceToHost));
+  gkb_cnn* nn = const_cast<gkb_cnn*>(n);
+  CNNCK(cnn_copy(nn, p.data(), n->params, n->np * 4, hipMemcpyDeviceToHost));
+  CNNCK(cnn_copy(nn, m.data(), n->m, n->np * 4, hipMemcpyDeviceToHost));
+  CNNCK(cnn_copy(nn, v.data(), n->v, n->np * 4, hipMemcpyDeviceToHost));
   FILE* f = std::fopen(path, "wb");
   if (!f) return GKB_EINVAL;
   const char magic[8] = {'G', 'K', 'B', 'C', 'N', 'N', '0', '1'};
@@ -788,9 +804,9 @@ int gkb_cnn_load(const char* path, gkb_cnn** out) {
     return GKB_EINVAL;
   }
   n->adam_t = hdr[3];
-  if (hipMemcpy(n->params, p.data(), n->np * 4, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(n->m, m.data(), n->np * 4, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(n->v, v.data(), n->np * 4, hipMemcpyHostToDevice) != hipSuccess) {
+  if (cnn_copy(n, n->params, p.data(), n->np * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      cnn_copy(n, n->m, m.data(), n->np * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      cnn_copy(n, n->v, v.data(), n->np * 4, hipMemcpyHostToDevice) != hipSuccess) {
     gkb_cnn_destroy(n);
     return GKB_EHIP;
   }

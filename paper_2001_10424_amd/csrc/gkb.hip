@@ -121,13 +121,14 @@ struct Alloc {
   std::vector<void*> ptrs;
   size_t bytes = 0;
   size_t cap = 0;
+  hipStream_t s = nullptr;  // the context stream: zero fills are ordered on it
   int get(void** out, size_t b) {
     if (cap && bytes + b > cap) return GKB_ENOMEM;
     void* q = nullptr;
     if (hipMalloc(&q, std::max<size_t>(b, 256)) != hipSuccess) return GKB_ENOMEM;
     ptrs.push_back(q);
     // zero-filled: faces that no kernel writes (Dirichlet faces) read as 0
-    if (hipMemset(q, 0, std::max<size_t>(b, 256)) != hipSuccess) return GKB_EHIP;
+    if (hipMemsetAsync(q, 0, std::max<size_t>(b, 256), s) != hipSuccess) return GKB_EHIP;
     bytes += b;
     *out = q;
     return GKB_OK;
@@ -642,11 +643,21 @@ void edge_viscosity(const Grid& g, const std::vector<double>& mu, int B, std::ve
       }
 }
 
+// Host <-> device copy ordered on the context's stream and complete on return.
+// The context stream is non-blocking, so it is not ordered with the null
+// stream that a plain hipMemcpy uses (a pageable upload may also return
+// before its DMA has landed).
+int copy_sync(gkb_ctx* c, void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+  HIPCK(hipMemcpyAsync(dst, src, bytes, kind, c->cs));
+  HIPCK(hipStreamSynchronize(c->cs));
+  return GKB_OK;
+}
+
 template <typename T>
 int upload(gkb_ctx* c, const std::vector<double>& h, T** out) {
   std::vector<T> tmp(h.begin(), h.end());
   CK(c->mem.arr(out, tmp.size()));
-  HIPCK(hipMemcpy(*out, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice));
+  CK(copy_sync(c, *out, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice));
   return GKB_OK;
 }
 
@@ -737,7 +748,7 @@ int edge_setup_level(gkb_ctx* c, int l, double* psi, double* t, double* dg, doub
   HIPCK(hipMemcpyAsync(dh.data(), dg, ne * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCK(hipStreamSynchronize(s));
   for (auto& v : dh) v = v > 0.0 ? 1.0 / v : 0.0;
-  HIPCK(hipMemcpy(dg, dh.data(), ne * sizeof(double), hipMemcpyHostToDevice));
+  CK(copy_sync(c, dg, dh.data(), ne * sizeof(double), hipMemcpyHostToDevice));
   // power iteration from D_e^-1 C^T (seeded random faces)
   std::vector<double> f0(m);
   unsigned sd = 54321u;
@@ -745,7 +756,7 @@ int edge_setup_level(gkb_ctx* c, int l, double* psi, double* t, double* dg, doub
     sd = sd * 1664525u + 1013904223u;
     v = (sd >> 8) * (1.0 / 16777216.0) - 0.5;
   }
-  HIPCK(hipMemcpy(cf, f0.data(), m * sizeof(double), hipMemcpyHostToDevice));
+  CK(copy_sync(c, cf, f0.data(), m * sizeof(double), hipMemcpyHostToDevice));
   k_edge_ct<double, DIM><<<cg, kBlock, 0, s>>>(g, cf, dg, 1.0, psi, nullptr);
   double lam = 1.0;
   for (int it = 0; it < 30; ++it) {
@@ -826,7 +837,7 @@ int build_inner(gkb_ctx* c, Inner<T>& in, const std::vector<Coef<T>>& coef) {
   HIPCK(hipMemcpyAsync(dh.data(), in.dinv, m * sizeof(T), hipMemcpyDeviceToHost, c->cs));
   HIPCK(hipStreamSynchronize(c->cs));
   for (auto& v : dh) v = v != T(0) ? T(1) / v : T(0);
-  HIPCK(hipMemcpy(in.dinv, dh.data(), m * sizeof(T), hipMemcpyHostToDevice));
+  CK(copy_sync(c, in.dinv, dh.data(), m * sizeof(T), hipMemcpyHostToDevice));
   in.ready = true;
   return GKB_OK;
 }
@@ -838,6 +849,7 @@ int setup_impl(gkb_ctx* c, const gkb_grid* grid, const double* visc, double eta,
   c->mem.cap = opt->max_workspace_bytes;
   c->us = static_cast<hipStream_t>(opt->hip_stream);
   HIPCK(hipStreamCreateWithFlags(&c->cs, hipStreamNonBlocking));
+  c->mem.s = c->cs;
   HIPCK(hipEventCreateWithFlags(&c->ev, hipEventDisableTiming));
   int n[3] = {grid->n[0], grid->n[1], grid->dim == 3 ? grid->n[2] : 1};
   c->g = make_grid(grid->dim, n, grid->h, grid->bc, grid->pin_cell);
@@ -957,7 +969,7 @@ int setup_impl(gkb_ctx* c, const gkb_grid* grid, const double* visc, double eta,
       s = s * 1664525u + 1013904223u;
       v = 0.5 + (s >> 8) * (1.0 / 16777216.0);
     }
-    HIPCK(hipMemcpy(xa, x0.data(), g.m_full * sizeof(double), hipMemcpyHostToDevice));
+    CK(copy_sync(c, xa, x0.data(), g.m_full * sizeof(double), hipMemcpyHostToDevice));
     double lam = 1.0;
     for (int it = 0; it < 40; ++it) {
       face_op<double, kDinvM>(c, op, fl, xa, nullptr, ya, 0.0, c->part[0], nullptr);
@@ -1010,7 +1022,7 @@ int setup_impl(gkb_ctx* c, const gkb_grid* grid, const double* visc, double eta,
     for (int a = 0; a < nu; ++a)
       for (int b2 = 0; b2 < nu; ++b2) Minv[(size_t)idx[a] * mcf + idx[b2]] = Mu[(size_t)a * nu + b2];
     CK(c->mem.arr(&c->Minv, (size_t)mcf * mcf));
-    HIPCK(hipMemcpy(c->Minv, Minv.data(), Minv.size() * sizeof(double), hipMemcpyHostToDevice));
+    CK(copy_sync(c, c->Minv, Minv.data(), Minv.size() * sizeof(double), hipMemcpyHostToDevice));
     c->mc = mcf;
   }
   if (opt->precision == GKB_MIXED) CK(build_inner<float>(c, c->in32, c->coef32));
@@ -1110,6 +1122,7 @@ int gkb_solve(gkb_ctx* c, const double* g, const double* r, double tol, int dela
   c->stats.fallbacks = 0;
   c->stats.learned_solves = 0;
   c->stats.residual = -1.0;
+  c->stats.learned_gain = -1.0;
   learned_reset(c->learned);
   int K = 0, rc;
   double est = 0.0;

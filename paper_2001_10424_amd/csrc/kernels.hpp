@@ -59,15 +59,17 @@ struct PcgState {
   double rz_prev;   // flexible CG
   double rt2;       // squared norm of the post-V-cycle residual (learned path)
   double theta;     // energy-optimal weight of the network correction
-  double ring[10];  // r.r of the last 10 iterations (stagnation test)
+  double gain;      // error energy removed by that step, (c.rt)^2 / (c.Mc)
+  double gain_sum;  // sum over network applications of gain / (r.V(r))
+  double ring[10];  // r.r sampled every 5 iterations (stagnation test)
   int it, maxit, done, status, nonfinite;
   int fallback;     // learned preconditioner switched off for this solve
-  int stagnant;     // no decrease of r.r over the last 10 iterations
+  int stagnant;     // no decrease of r.r over the last 50 iterations
   int use_zv;       // direction from the V-cycle alone
   int fallbacks;
-  int fb_it;        // iteration and cause (1 descent, 2 stagnation) of the fallback
-  int fb_reason;
-  int pad;
+  int fb_it;        // iteration and cause of the fallback (1 descent,
+  int fb_reason;    // 2 stagnation, 3 gain below the threshold)
+  int gain_n;       // network applications counted in gain_sum
 };
 
 // ------------------------------------------------- face-operator kernels
@@ -389,7 +391,8 @@ __global__ __launch_bounds__(kFinal) void k_pcg_start(PcgState* st, const double
     st->status = 0;
     st->fallback = st->stagnant = st->use_zv = st->fallbacks = 0;
     st->fb_it = st->fb_reason = 0;
-    st->theta = 0.0;
+    st->theta = st->gain = st->gain_sum = 0.0;
+    st->gain_n = 0;
     for (int i = 0; i < 10; ++i) st->ring[i] = 0.0;
   }
 }

@@ -13,6 +13,9 @@ struct Learned {
   // guards, the rest of the gkb_solve uses MG-PCG
   int fails = 0;
   bool off = false;
+  // network energy gain relative to the V-cycle over the current gkb_solve
+  double gain_sum = 0.0;
+  long gain_n = 0;
   double lam = 1.0;       // mean diag(W) over the unknown faces
   long m_unknown = 1;
   float* logmu = nullptr;  // cell log-viscosity (input channel), zeros for mu = 1
@@ -28,6 +31,12 @@ struct Learned {
 };
 
 namespace gkb {
+
+// The network correction is kept only while the error energy its step removes
+// is at least this fraction of what the V-cycle step removes (r.V(r)): one
+// application costs about as much as a V-cycle, so a smaller gain cannot pay
+// for itself.
+constexpr double kMinGain = 0.05;
 
 // squared norm of the post-V-cycle residual from block partials
 __global__ __launch_bounds__(kFinal) void k_set_rt2(PcgState* st, const double* part, int n) {
@@ -105,7 +114,11 @@ __global__ __launch_bounds__(kFinal) void k_set_theta(PcgState* st, const double
   const double crt = sum_partials(p_crt, n1, sh);
   __syncthreads();
   const double cmc = sum_partials(p_cmc, n2, sh);
-  if (threadIdx.x == 0) st->theta = (cmc > 0.0 && isfinite(crt / cmc)) ? crt / cmc : 0.0;
+  if (threadIdx.x == 0) {
+    const bool ok = cmc > 0.0 && isfinite(crt / cmc);
+    st->theta = ok ? crt / cmc : 0.0;
+    st->gain = ok ? crt * crt / cmc : 0.0;
+  }
 }
 
 // z = zv + theta c (z = zv during fallback); partials r.z, z.r_prev, zv.r_prev
@@ -162,9 +175,10 @@ __global__ __launch_bounds__(256) void k_fcg_xr(int n, const PcgState* __restric
 }
 
 // choose the direction: the CNN-corrected z unless it fails the descent test
-// (r.z <= 0) or the residual stagnated (no decrease over 10 iterations); then
-// fall back to the V-cycle alone for the rest of the solve, restarting CG.
-// first = 1 at the start of a solve.
+// (r.z <= 0), the residual stagnated (no decrease over 50 iterations) or the
+// network step removes less than kMinGain of the V-cycle step's error energy;
+// then fall back to the V-cycle alone for the rest of the solve, restarting
+// CG.  first = 1 at the start of a solve.
 __global__ __launch_bounds__(kFinal) void k_fcg_beta(PcgState* st, const double* p_rzv, int nv,
                                                      const double* p_rz, const double* p_zrp,
                                                      const double* p_zvrp, int nu, int first) {
@@ -179,12 +193,18 @@ __global__ __launch_bounds__(kFinal) void k_fcg_beta(PcgState* st, const double*
   const double zvrp = sum_partials(p_zvrp, nu, sh);
   if (threadIdx.x != 0) return;
   bool restart = first != 0;
-  if (!st->fallback && (!(rz > 0.0) || st->stagnant)) {
-    st->fallback = 1;
-    st->fallbacks += 1;
-    st->fb_it = st->it;
-    st->fb_reason = (rz > 0.0) ? 2 : 1;
-    restart = true;
+  if (!st->fallback) {
+    const double ratio = rzv > 0.0 ? st->gain / rzv : 0.0;
+    st->gain_sum += ratio;
+    st->gain_n += 1;
+    const int reason = !(rz > 0.0) ? 1 : (st->stagnant ? 2 : (ratio < kMinGain ? 3 : 0));
+    if (reason) {
+      st->fallback = 1;
+      st->fallbacks += 1;
+      st->fb_it = st->it;
+      st->fb_reason = reason;
+      restart = true;
+    }
   }
   st->use_zv = st->fallback;
   const double rz_use = st->fallback ? rzv : rz;
@@ -245,6 +265,8 @@ void learned_reset(Learned* L) {
   if (L) {
     L->fails = 0;
     L->off = false;
+    L->gain_sum = 0.0;
+    L->gain_n = 0;
   }
 }
 bool learned_capturing(Learned* L) { return L && L->cap_in && L->cap_n < L->cap_max; }
@@ -259,10 +281,10 @@ int learned_create(gkb_ctx* c) {
   CK(c->mem.arr(&L->logmu, c->g.n_cells));
   if (c->varmu) {
     std::vector<double> mh(c->g.n_cells);
-    HIPCK(hipMemcpy(mh.data(), c->coef64[0].mu, mh.size() * 8, hipMemcpyDeviceToHost));
+    CK(copy_sync(c, mh.data(), c->coef64[0].mu, mh.size() * 8, hipMemcpyDeviceToHost));
     std::vector<float> lm(mh.size());
     for (size_t i = 0; i < mh.size(); ++i) lm[i] = float(std::log(mh[i]));
-    HIPCK(hipMemcpy(L->logmu, lm.data(), lm.size() * 4, hipMemcpyHostToDevice));
+    CK(copy_sync(c, L->logmu, lm.data(), lm.size() * 4, hipMemcpyHostToDevice));
   }
   // lambda = mean of diag(W) over the unknown faces: the error a V-cycle
   // leaves behind is mostly divergence free, where M acts as W
@@ -417,13 +439,17 @@ int learned_solve(gkb_ctx* c, const double* f, double* x_out, double tol, int* i
   }
   k_cast<T, double><<<vb, kBlock, 0, s>>>(n, in.x, x_out);
   if (std::getenv("GKB_DEBUG"))
-    std::fprintf(stderr, "learned solve: it %d fallback %d at it %d reason %d theta %.3e\n",
-                 hs.it, hs.fallbacks, hs.fb_it, hs.fb_reason, hs.theta);
+    std::fprintf(stderr, "learned solve: it %d fallback %d at it %d reason %d theta %.3e gain %.3e\n",
+                 hs.it, hs.fallbacks, hs.fb_it, hs.fb_reason, hs.theta,
+                 hs.gain_n ? hs.gain_sum / hs.gain_n : -1.0);
   if (iters) *iters = hs.it;
   c->stats.inner_iterations += hs.it;
   c->stats.inner_solves += 1;
   c->stats.learned_solves += 1;
   c->stats.fallbacks += hs.fallbacks;
+  L->gain_sum += hs.gain_sum;
+  L->gain_n += hs.gain_n;
+  c->stats.learned_gain = L->gain_n ? L->gain_sum / L->gain_n : -1.0;
   if (hs.fallbacks > 0) {
     if (++L->fails >= 2) L->off = true;
   } else {

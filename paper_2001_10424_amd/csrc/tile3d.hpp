@@ -20,8 +20,11 @@
 
 namespace gkb {
 
-constexpr int kTX = 64;          // tile width (cells) = threads in x
-constexpr int kTYT = 4;          // threads in y
+#ifndef GKB_TILE_X
+#define GKB_TILE_X 64
+#endif
+constexpr int kTX = GKB_TILE_X;  // tile width (cells) = threads in x
+constexpr int kTYT = 256 / kTX;  // threads in y
 constexpr int kRPT = 2;          // rows per thread
 constexpr int kTY = kTYT * kRPT; // tile height (cells)
 constexpr int kLX = kTX + 2;
@@ -85,7 +88,17 @@ __device__ __forceinline__ double tile_finish(int f, T mx, T d, T xf, T bf, T* _
 }
 
 // FINE only separates the finest-grid launches from the coarse-level ones in
-// kernel traces; the code is the same
+// kernel traces; the code is the same.
+//
+// Latency hiding: every global load is unconditional from an address that is
+// always valid (indices outside the grid or on non-unknown faces are clamped
+// to the first entry of the array) and the mask is applied when the value is
+// stored to LDS, so no load sits under a branch.  Loads run two planes ahead:
+// while plane k is computed, the x values of plane k+2 and b of plane k+1 are
+// already in flight and plane k+3 (x) and k+2 (b) are issued.  Two register
+// sets of each take turns (the plane loop is unrolled by two), so consuming
+// one never waits for the loads into the other; the prologue issues its four
+// planes at once.
 template <typename T, bool VARMU, int MODE, bool FINE>
 __global__ __launch_bounds__(256) void k_tile3d(Op<T> op, const T* __restrict__ x,
                                                 const T* __restrict__ b, T* __restrict__ y,
@@ -104,54 +117,100 @@ __global__ __launch_bounds__(256) void k_tile3d(Op<T> op, const T* __restrict__ 
   const int by = rest % gridDim.y, bz = rest / gridDim.y;
   const int i0 = bx * kTX, j0 = by * kTY, k0 = bz * tz;
   const int k1 = min(k0 + tz, nz);
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
   const bool unk_u0 = G.bc[0] == kNat, unk_v0 = G.bc[2] == kNat, unk_w0 = G.bc[4] == kNat;
+  // plane strides of the three face arrays
+  const int pu = G.ext[0][0] * G.ext[0][1], pv = G.ext[1][0] * G.ext[1][1],
+            pw = G.ext[2][0] * G.ext[2][1];
 
-  // plane staging is split into a global fetch into registers and an LDS
-  // store, so that the fetch of plane k+2 is in flight while plane k is
-  // computed
+  // staged halo elements of this thread: in-plane array index (clamped) and
+  // validity bits (u, v, w per element), fixed for the whole block
   constexpr int kPer = (kLX * kLY + 255) / 256;
-  T fu[kPer], fv[kPer], fw[kPer];
-  auto fetch_plane = [&](int k) {
+  int hu[kPer], hv[kPer], hw[kPer];
+  unsigned hmask = 0;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int e = threadIdx.x + q * 256;
+    const int jj = e / kLX, ii = e - jj * kLX;
+    const int i = i0 - 1 + ii, j = j0 - 1 + jj;
+    const bool in = e < kLX * kLY && j >= 0 && j < ny && i >= 0 && i < nx;
+    const bool ou = in && (i > 0 || unk_u0), ov = in && (j > 0 || unk_v0);
+    hu[q] = G.off[0] + (ou ? j * G.ext[0][0] + i : 0);
+    hv[q] = G.off[1] + (ov ? j * G.ext[1][0] + i : 0);
+    hw[q] = G.off[2] + (in ? j * G.ext[2][0] + i : 0);
+    hmask |= (ou ? 1u : 0u) << (3 * q);
+    hmask |= (ov ? 2u : 0u) << (3 * q);
+    hmask |= (in ? 4u : 0u) << (3 * q);
+  }
+  typedef T FRegs[3][kPer];
+  auto fetch_plane = [&](int k, FRegs& F) {
+    const int kk = min(max(k, 0), nz - 1);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      F[0][q] = x[hu[q] + kk * pu];
+      F[1][q] = x[hv[q] + kk * pv];
+      F[2][q] = x[hw[q] + kk * pw];
+    }
+  };
+  auto store_plane = [&](int s, int k, const FRegs& F) {
+    const bool kin = k >= 0 && k < nz;
+    const bool kw = kin && (k > 0 || unk_w0);
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const int e = threadIdx.x + q * 256;
-      fu[q] = fv[q] = fw[q] = T(0);
       if (e < kLX * kLY) {
         const int jj = e / kLX, ii = e - jj * kLX;
-        const int i = i0 - 1 + ii, j = j0 - 1 + jj;
-        const bool jin = j >= 0 && j < ny, iin = i >= 0 && i < nx;
-        if (k >= 0 && k < nz) {
-          if (jin && iin && (i > 0 || unk_u0)) fu[q] = x[fidx<0>(G, i, j, k)];
-          if (iin && jin && (j > 0 || unk_v0)) fv[q] = x[fidx<1>(G, i, j, k)];
-          if (iin && jin && (k > 0 || unk_w0)) fw[q] = x[fidx<2>(G, i, j, k)];
-        }
+        const unsigned m = hmask >> (3 * q);
+        S.u[s][jj][ii] = (kin && (m & 1u)) ? F[0][q] : T(0);
+        S.v[s][jj][ii] = (kin && (m & 2u)) ? F[1][q] : T(0);
+        S.w[s][jj][ii] = (kw && (m & 4u)) ? F[2][q] : T(0);
       }
     }
-  };
-  auto store_plane = [&](int s) {
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = threadIdx.x + q * 256;
-      if (e < kLX * kLY) {
-        const int jj = e / kLX, ii = e - jj * kLX;
-        S.u[s][jj][ii] = fu[q];
-        S.v[s][jj][ii] = fv[q];
-        S.w[s][jj][ii] = fw[q];
-      }
-    }
-  };
-  auto load_plane = [&](int k, int s) {
-    fetch_plane(k);
-    store_plane(s);
   };
   auto cell_ok = [&](int i, int j, int k) {
     return i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz && cidx(G, i, j, k) != G.pin;
   };
 
+  // this thread's faces: in-plane index of u, v, w (clamped when outside)
+  int fo[kRPT][3];
+#pragma unroll
+  for (int r = 0; r < kRPT; ++r) {
+    const int i = i0 + tx, j = j0 + ty + r * kTYT;
+    const bool in = i < nx && j < ny;
+    fo[r][0] = G.off[0] + (in ? j * G.ext[0][0] + i : 0);
+    fo[r][1] = G.off[1] + (in ? j * G.ext[1][0] + i : 0);
+    fo[r][2] = G.off[2] + (in ? j * G.ext[2][0] + i : 0);
+  }
+  typedef T BRegs[kRPT][3];
+  auto fetch_b = [&](int k, BRegs& bb) {
+    if (!reads_b<MODE>()) return;
+    const int kk = min(k, nz - 1);
+#pragma unroll
+    for (int r = 0; r < kRPT; ++r) {
+      bb[r][0] = b[fo[r][0] + kk * pu];
+      bb[r][1] = b[fo[r][1] + kk * pv];
+      bb[r][2] = b[fo[r][2] + kk * pw];
+    }
+  };
+
   T up[kRPT], vp[kRPT], wp[kRPT], cdp[kRPT];
-  load_plane(k0 - 1, 1);
-  load_plane(k0, 0);
+  BRegs bA, bB;
+#pragma unroll
+  for (int r = 0; r < kRPT; ++r)
+    bA[r][0] = bA[r][1] = bA[r][2] = bB[r][0] = bB[r][1] = bB[r][2] = T(0);
+  FRegs FA, FB;
+  fetch_plane(k0 - 1, FA);
+  fetch_plane(k0, FB);
+  store_plane(1, k0 - 1, FA);
+  store_plane(0, k0, FB);
+  // planes k0+1 (FA) and k0+2 (FB), b of planes k0 (bA) and k0+1 (bB)
+  // (prefetches past the block's last plane read clamped, valid addresses:
+  // issuing them unconditionally keeps the number of loads in flight fixed,
+  // so each wait can leave the younger prefetches outstanding)
+  fetch_plane(k0 + 1, FA);
+  fetch_plane(k0 + 2, FB);
+  fetch_b(k0, bA);
+  fetch_b(k0 + 1, bB);
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kRPT; ++r) {
@@ -166,27 +225,16 @@ __global__ __launch_bounds__(256) void k_tile3d(Op<T> op, const T* __restrict__ 
                  : T(0);
   }
   __syncthreads();
-  fetch_plane(k0 + 1);
 
   const T eta = op.eta, ih2 = op.ih2;
   double part = 0.0;
-  for (int k = k0; k < k1; ++k) {
+  // one z-plane: x of plane k+1 is in F and b of plane k in bc; F is
+  // refilled with plane k+3 and bc with b of plane k+2
+  auto step = [&](int k, FRegs& F, BRegs& bc) {
     const int s = (k - k0) & 1, s1 = s ^ 1;
-    store_plane(s1);  // plane k+1, fetched during the previous plane
-    // b of this thread's faces
-    T bu[kRPT], bv[kRPT], bw[kRPT];
-#pragma unroll
-    for (int r = 0; r < kRPT; ++r) {
-      bu[r] = bv[r] = bw[r] = T(0);
-      const int i = i0 + tx, j = j0 + ty + r * kTYT;
-      if (reads_b<MODE>() && i < nx && j < ny) {
-        bu[r] = b[fidx<0>(G, i, j, k)];
-        bv[r] = b[fidx<1>(G, i, j, k)];
-        bw[r] = b[fidx<2>(G, i, j, k)];
-      }
-    }
+    store_plane(s1, k + 1, F);
     __syncthreads();
-    if (k + 1 < k1) fetch_plane(k + 2);  // consumed at the top of the next plane
+    fetch_plane(k + 3, F);
     // divergence sums of plane k for cells (i0-1 .. i0+63) x (j0-1 .. j0+7)
     for (int e = threadIdx.x; e < (kTX + 1) * (kTY + 1); e += 256) {
       const int cj = e / (kTX + 1), ci = e - cj * (kTX + 1);
@@ -207,7 +255,7 @@ __global__ __launch_bounds__(256) void k_tile3d(Op<T> op, const T* __restrict__ 
         const bool okR = cell_ok(i, j, k);
         // ---- u-face (i, j, k): normal x
         {
-          const int f = fidx<0>(G, i, j, k);
+          const int f = fo[r][0] + k * pu;
           if (i > 0 || unk_u0) {
             const T xf = S.u[s][jj][ii];
             T acc = T(0), d = T(0);
@@ -233,14 +281,14 @@ __global__ __launch_bounds__(256) void k_tile3d(Op<T> op, const T* __restrict__ 
               acc += eta * (cR - cL);
               d += eta * T(cnt);
             }
-            part += tile_finish<T, MODE>(f, acc * ih2, d * ih2, xf, bu[r], y, omega);
+            part += tile_finish<T, MODE>(f, acc * ih2, d * ih2, xf, bc[r][0], y, omega);
           } else {
             y[f] = T(0);
           }
         }
         // ---- v-face (i, j, k): normal y
         {
-          const int f = fidx<1>(G, i, j, k);
+          const int f = fo[r][1] + k * pv;
           if (j > 0 || unk_v0) {
             const T xf = S.v[s][jj][ii];
             T acc = T(0), d = T(0);
@@ -266,14 +314,14 @@ __global__ __launch_bounds__(256) void k_tile3d(Op<T> op, const T* __restrict__ 
               acc += eta * (cR - cL);
               d += eta * T(cnt);
             }
-            part += tile_finish<T, MODE>(f, acc * ih2, d * ih2, xf, bv[r], y, omega);
+            part += tile_finish<T, MODE>(f, acc * ih2, d * ih2, xf, bc[r][1], y, omega);
           } else {
             y[f] = T(0);
           }
         }
         // ---- w-face (i, j, k): normal z
         {
-          const int f = fidx<2>(G, i, j, k);
+          const int f = fo[r][2] + k * pw;
           if (k > 0 || unk_w0) {
             const T xf = S.w[s][jj][ii];
             T acc = T(0), d = T(0);
@@ -298,22 +346,27 @@ __global__ __launch_bounds__(256) void k_tile3d(Op<T> op, const T* __restrict__ 
               acc += eta * (cR - cdp[r]);
               d += eta * T(cnt);
             }
-            part += tile_finish<T, MODE>(f, acc * ih2, d * ih2, xf, bw[r], y, omega);
+            part += tile_finish<T, MODE>(f, acc * ih2, d * ih2, xf, bc[r][2], y, omega);
           } else {
             y[f] = T(0);
           }
         }
         // upper boundary faces are Dirichlet faces: keep them zero
-        if (i == nx - 1) y[fidx<0>(G, nx, j, k)] = T(0);
-        if (j == ny - 1) y[fidx<1>(G, i, ny, k)] = T(0);
-        if (k == nz - 1) y[fidx<2>(G, i, j, nz)] = T(0);
+        if (i == nx - 1) y[fo[r][0] + k * pu + 1] = T(0);
+        if (j == ny - 1) y[fo[r][1] + k * pv + nx] = T(0);
+        if (k == nz - 1) y[fo[r][2] + nz * pw] = T(0);
         up[r] = S.u[s][jj][ii];
         vp[r] = S.v[s][jj][ii];
         wp[r] = S.w[s][jj][ii];
         cdp[r] = cR;
       }
     }
+    fetch_b(k + 2, bc);
     __syncthreads();
+  };
+  for (int k = k0; k < k1; k += 2) {
+    step(k, FA, bA);
+    if (k + 1 < k1) step(k + 1, FB, bB);
   }
   constexpr bool kRed = MODE == kApplyDot || MODE == kJacobiDot || MODE == kDinvM || MODE == kResidDot;
   if (kRed) {

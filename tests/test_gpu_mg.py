@@ -65,8 +65,13 @@ def test_vcycle_symmetric_positive(name, grid, eta, varmu, smoother):
     s.close()
 
 
+TILED_CASES = MG_CASES[:2] + [
+    ("3d_lower_natural", P.Grid(3, (16, 24, 16), 1 / 16, (N, D, D, D, D, D), -1), 10.0, True),
+]
+
+
 @pytest.mark.parametrize("smoother", ["jacobi", "hybrid"])
-@pytest.mark.parametrize("name,grid,eta,varmu", MG_CASES[:2], ids=[c[0] for c in MG_CASES[:2]])
+@pytest.mark.parametrize("name,grid,eta,varmu", TILED_CASES, ids=[c[0] for c in TILED_CASES])
 def test_tiled_matches_generic(name, grid, eta, varmu, smoother):
     """The LDS-tiled 3D kernel and the generic face kernel compute the same
     operator, V-cycle (every smoother / residual mode) and inner solve."""
