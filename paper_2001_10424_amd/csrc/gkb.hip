@@ -84,7 +84,9 @@ FaceLaunch face_launch(const Grid& g, int kz, int stencil = 0) {
     const char* e = std::getenv("GKB_TILE_MIN");
     return e ? std::atol(e) : 0L;
   }();
-  if (stencil == 0 && g.dim == 3 && upper_dir && g.n_cells >= tile_min) {
+  // (32-bit buffer offsets: face arrays below 2 GiB in FP64)
+  if (stencil == 0 && g.dim == 3 && upper_dir && g.n_cells >= tile_min &&
+      (long)g.m_full * 8 < (1L << 31)) {
     if (g_tz == 0) {
       const char* e = std::getenv("GKB_TZ");
       g_tz = e ? std::max(1, std::atoi(e)) : -1;
@@ -431,8 +433,10 @@ int inner_solve(gkb_ctx* c, const double* f, double* x_out, double tol, int* ite
   if (!in.ready) return GKB_EINVAL;
   if (learned_capturing(c->learned) && c->opt.inner != GKB_INNER_JACOBI)
     return capture_solve<T>(c, f, x_out, tol, iters);
-  if (c->opt.inner == GKB_INNER_LEARNED && c->learned && learned_enabled(c->learned))
-    return learned_solve<T>(c, f, x_out, tol, iters);
+  if (c->opt.inner == GKB_INNER_LEARNED && c->learned && learned_enabled(c->learned)) {
+    const int rc = learned_solve<T>(c, f, x_out, tol, iters);
+    if (rc != kLearnedDeclined) return rc;
+  }
   const Level<T>& L0 = in.lv[0];
   const int n = L0.g.m_full, vb = vec_blocks(n);
   hipStream_t s = c->cs;

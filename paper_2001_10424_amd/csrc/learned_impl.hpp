@@ -9,9 +9,8 @@
 
 struct Learned {
   gkb_cnn* net = nullptr;
-  // after two consecutive inner solves whose network direction failed the
-  // guards, the rest of the gkb_solve uses MG-PCG
-  int fails = 0;
+  // once the network direction has failed a guard, the rest of the
+  // gkb_solve uses MG-PCG
   bool off = false;
   // network energy gain relative to the V-cycle over the current gkb_solve
   double gain_sum = 0.0;
@@ -263,7 +262,6 @@ namespace {
 bool learned_enabled(Learned* L) { return L && L->net && !L->off; }
 void learned_reset(Learned* L) {
   if (L) {
-    L->fails = 0;
     L->off = false;
     L->gain_sum = 0.0;
     L->gain_n = 0;
@@ -413,6 +411,25 @@ int learned_solve(gkb_ctx* c, const double* f, double* x_out, double tol, int* i
                                   c->part[5], nu, 1);
   k_fill<T><<<vb, kBlock, 0, s>>>(n, T(0), in.p);
   k_fcg_p<T><<<vb, 256, 0, s>>>(n, in.st, in.z, zv, in.p);
+  PcgState hs;
+  // a network that fails the guards at its first application is not used for
+  // this solve (plain MG-PCG has no flexible-CG overhead), nor for the rest
+  // of the gkb_solve
+  HIPCK(hipMemcpyAsync(c->hbuf, in.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  std::memcpy(&hs, c->hbuf, sizeof(PcgState));
+  if (hs.fallback) {
+    c->stats.learned_solves += 1;
+    c->stats.fallbacks += 1;
+    L->gain_sum += hs.gain_sum;
+    L->gain_n += hs.gain_n;
+    c->stats.learned_gain = L->gain_n ? L->gain_sum / L->gain_n : -1.0;
+    L->off = true;
+    if (std::getenv("GKB_DEBUG"))
+      std::fprintf(stderr, "learned solve declined: reason %d gain %.3e\n", hs.fb_reason,
+                   hs.gain_n ? hs.gain_sum / hs.gain_n : -1.0);
+    return kLearnedDeclined;
+  }
   const int chunk = std::max(1, c->opt.check_every);
   if (c->opt.use_graphs) {
     if (!(in.graph && in.graph_len == chunk && in.graph_mode == GKB_INNER_LEARNED)) {
@@ -428,7 +445,6 @@ int learned_solve(gkb_ctx* c, const double* f, double* x_out, double tol, int* i
       in.graph_mode = GKB_INNER_LEARNED;
     }
   }
-  PcgState hs;
   for (;;) {
     if (c->opt.use_graphs) HIPCK(hipGraphLaunch(in.graph, s));
     else fcg_iterations<T>(c, in, chunk);
@@ -450,11 +466,7 @@ int learned_solve(gkb_ctx* c, const double* f, double* x_out, double tol, int* i
   L->gain_sum += hs.gain_sum;
   L->gain_n += hs.gain_n;
   c->stats.learned_gain = L->gain_n ? L->gain_sum / L->gain_n : -1.0;
-  if (hs.fallbacks > 0) {
-    if (++L->fails >= 2) L->off = true;
-  } else {
-    L->fails = 0;
-  }
+  if (hs.fallbacks > 0) L->off = true;
   if (hs.nonfinite) return GKB_ENAN;
   if (hs.status == -5) return GKB_EINNER;
   return GKB_OK;

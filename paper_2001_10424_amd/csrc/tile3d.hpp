@@ -20,10 +20,7 @@
 
 namespace gkb {
 
-#ifndef GKB_TILE_X
-#define GKB_TILE_X 64
-#endif
-constexpr int kTX = GKB_TILE_X;  // tile width (cells) = threads in x
+constexpr int kTX = 64;          // tile width (cells) = threads in x
 constexpr int kTYT = 256 / kTX;  // threads in y
 constexpr int kRPT = 2;          // rows per thread
 constexpr int kTY = kTYT * kRPT; // tile height (cells)
@@ -39,24 +36,58 @@ struct TileLds {
 };
 
 // one axis of the viscous stencil; lo_in / hi_in: neighbour inside the array,
-// lo_wall / hi_wall: neighbour across a DIRICHLET wall (mirror ghost)
+// lo_wall / hi_wall: neighbour across a DIRICHLET wall (mirror ghost).
+// Branch-free: the neighbour values outside the array are zeros in LDS, so
+// their coefficients are selected instead of branched on.
 template <typename T>
 __device__ __forceinline__ void visc_axis(T xf, T vlo, T vhi, bool lo_in, bool hi_in, bool lo_wall,
                                           bool hi_wall, T klo, T khi, T wgt, T& acc, T& d) {
-  if (lo_in) {
-    acc += wgt * klo * (xf - vlo);
-    d += wgt * klo;
-  } else if (lo_wall) {
-    acc += T(2) * wgt * klo * xf;
-    d += T(2) * wgt * klo;
-  }
-  if (hi_in) {
-    acc += wgt * khi * (xf - vhi);
-    d += wgt * khi;
-  } else if (hi_wall) {
-    acc += T(2) * wgt * khi * xf;
-    d += T(2) * wgt * khi;
-  }
+  const T wlo = wgt * klo, whi = wgt * khi;
+  const T clo = lo_in ? wlo : T(0), chi = hi_in ? whi : T(0);
+  const T alo = lo_in ? wlo : (lo_wall ? T(2) * wlo : T(0));
+  const T ahi = hi_in ? whi : (hi_wall ? T(2) * whi : T(0));
+  acc += (alo + ahi) * xf - clo * vlo - chi * vhi;
+  d += alo + ahi;
+}
+
+// 1 / d for the Jacobi step: the hardware reciprocal in FP32 (about 1 ulp,
+// plenty for a smoother), exact division in FP64
+template <typename T>
+__device__ __forceinline__ T recip(T d) {
+  return T(1) / d;
+}
+template <>
+__device__ __forceinline__ float recip<float>(float d) {
+  return __builtin_amdgcn_rcpf(d);
+}
+
+// Raw buffer access: a scalar base (buffer resource) plus a per-lane 32-bit
+// byte offset and a uniform scalar byte offset, so an access costs no 64-bit
+// address arithmetic.  The tiled kernel is used only for face arrays below
+// 2 GiB, which keeps every offset in 31 bits.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, unsigned voff,
+                                                 unsigned soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, unsigned voff,
+                                                   unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, unsigned voff,
+                                          unsigned soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, unsigned voff,
+                                          unsigned soff) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
 }
 
 template <int MODE>
@@ -64,26 +95,28 @@ constexpr bool reads_b() {
   return MODE == kJacobi || MODE == kJacobiDot || MODE == kResid || MODE == kResidDot;
 }
 
-// bf: b at the face (prefetched by the caller when the mode reads b)
+// bf: b at the face (prefetched by the caller when the mode reads b); unk:
+// the face is an unknown (else 0 is written, computed values discarded);
+// the result goes to byte offset voff + soff of y
 template <typename T, int MODE>
-__device__ __forceinline__ double tile_finish(int f, T mx, T d, T xf, T bf, T* __restrict__ y,
-                                              T omega) {
+__device__ __forceinline__ double tile_finish(unsigned voff, unsigned soff, bool unk, T mx, T d,
+                                              T xf, T bf, __amdgpu_buffer_rsrc_t ry, T omega) {
   double part = 0.0;
   T out;
   if (MODE == kApply || MODE == kApplyDot) {
-    out = mx;
+    out = unk ? mx : T(0);
     if (MODE == kApplyDot) part = double(xf) * double(out);
   } else if (MODE == kJacobi || MODE == kJacobiDot) {
-    out = xf + omega * (bf - mx) / d;
+    out = unk ? xf + omega * (bf - mx) * recip(d) : T(0);
     if (MODE == kJacobiDot) part = double(bf) * double(out);
   } else if (MODE == kResid || MODE == kResidDot) {
-    out = bf - mx;
+    out = unk ? bf - mx : T(0);
     if (MODE == kResidDot) part = double(out) * double(out);
   } else {  // kDinvM
-    out = mx / d;
+    out = unk ? mx * recip(d) : T(0);
     part = double(out) * double(out);
   }
-  y[f] = out;
+  buf_store(out, ry, voff, soff);
   return part;
 }
 
@@ -99,8 +132,15 @@ __device__ __forceinline__ double tile_finish(int f, T mx, T d, T xf, T bf, T* _
 // sets of each take turns (the plane loop is unrolled by two), so consuming
 // one never waits for the loads into the other; the prologue issues its four
 // planes at once.
+// FP32: at least 4 waves per SIMD (4 blocks per CU, all of the 128^3 grid
+// in one round) fit in 128 VGPRs without spills (measured 17% faster than
+// leaving the register count free); FP64 spills under any cap and runs
+// fastest without one
+template <typename T>
+constexpr int kTileMinWaves = sizeof(T) == 4 ? 4 : 1;
+
 template <typename T, bool VARMU, int MODE, bool FINE>
-__global__ __launch_bounds__(256) void k_tile3d(Op<T> op, const T* __restrict__ x,
+__global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, const T* __restrict__ x,
                                                 const T* __restrict__ b, T* __restrict__ y,
                                                 T omega, int tz, double* __restrict__ partial,
                                                 const PcgState* __restrict__ st) {
@@ -122,11 +162,15 @@ __global__ __launch_bounds__(256) void k_tile3d(Op<T> op, const T* __restrict__ 
   // plane strides of the three face arrays
   const int pu = G.ext[0][0] * G.ext[0][1], pv = G.ext[1][0] * G.ext[1][1],
             pw = G.ext[2][0] * G.ext[2][1];
+  constexpr unsigned E = sizeof(T);
+  const unsigned bytes = unsigned(G.m_full) * E;
+  const __amdgpu_buffer_rsrc_t rx = buf_rsrc(x, bytes), ry = buf_rsrc(y, bytes);
+  const __amdgpu_buffer_rsrc_t rb = reads_b<MODE>() ? buf_rsrc(b, bytes) : rx;
 
-  // staged halo elements of this thread: in-plane array index (clamped) and
+  // staged halo elements of this thread: in-plane byte offset (clamped) and
   // validity bits (u, v, w per element), fixed for the whole block
   constexpr int kPer = (kLX * kLY + 255) / 256;
-  int hu[kPer], hv[kPer], hw[kPer];
+  unsigned hu[kPer], hv[kPer], hw[kPer];
   unsigned hmask = 0;
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
@@ -135,9 +179,9 @@ __global__ __launch_bounds__(256) void k_tile3d(Op<T> op, const T* __restrict__ 
     const int i = i0 - 1 + ii, j = j0 - 1 + jj;
     const bool in = e < kLX * kLY && j >= 0 && j < ny && i >= 0 && i < nx;
     const bool ou = in && (i > 0 || unk_u0), ov = in && (j > 0 || unk_v0);
-    hu[q] = G.off[0] + (ou ? j * G.ext[0][0] + i : 0);
-    hv[q] = G.off[1] + (ov ? j * G.ext[1][0] + i : 0);
-    hw[q] = G.off[2] + (in ? j * G.ext[2][0] + i : 0);
+    hu[q] = unsigned(G.off[0] + (ou ? j * G.ext[0][0] + i : 0)) * E;
+    hv[q] = unsigned(G.off[1] + (ov ? j * G.ext[1][0] + i : 0)) * E;
+    hw[q] = unsigned(G.off[2] + (in ? j * G.ext[2][0] + i : 0)) * E;
     hmask |= (ou ? 1u : 0u) << (3 * q);
     hmask |= (ov ? 2u : 0u) << (3 * q);
     hmask |= (in ? 4u : 0u) << (3 * q);
@@ -147,9 +191,9 @@ __global__ __launch_bounds__(256) void k_tile3d(Op<T> op, const T* __restrict__ 
     const int kk = min(max(k, 0), nz - 1);
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-      F[0][q] = x[hu[q] + kk * pu];
-      F[1][q] = x[hv[q] + kk * pv];
-      F[2][q] = x[hw[q] + kk * pw];
+      F[0][q] = buf_load<T>(rx, hu[q], unsigned(kk * pu) * E);
+      F[1][q] = buf_load<T>(rx, hv[q], unsigned(kk * pv) * E);
+      F[2][q] = buf_load<T>(rx, hw[q], unsigned(kk * pw) * E);
     }
   };
   auto store_plane = [&](int s, int k, const FRegs& F) {
@@ -171,15 +215,15 @@ __global__ __launch_bounds__(256) void k_tile3d(Op<T> op, const T* __restrict__ 
     return i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz && cidx(G, i, j, k) != G.pin;
   };
 
-  // this thread's faces: in-plane index of u, v, w (clamped when outside)
-  int fo[kRPT][3];
+  // this thread's faces: in-plane byte offset of u, v, w (clamped when outside)
+  unsigned fo[kRPT][3];
 #pragma unroll
   for (int r = 0; r < kRPT; ++r) {
     const int i = i0 + tx, j = j0 + ty + r * kTYT;
     const bool in = i < nx && j < ny;
-    fo[r][0] = G.off[0] + (in ? j * G.ext[0][0] + i : 0);
-    fo[r][1] = G.off[1] + (in ? j * G.ext[1][0] + i : 0);
-    fo[r][2] = G.off[2] + (in ? j * G.ext[2][0] + i : 0);
+    fo[r][0] = unsigned(G.off[0] + (in ? j * G.ext[0][0] + i : 0)) * E;
+    fo[r][1] = unsigned(G.off[1] + (in ? j * G.ext[1][0] + i : 0)) * E;
+    fo[r][2] = unsigned(G.off[2] + (in ? j * G.ext[2][0] + i : 0)) * E;
   }
   typedef T BRegs[kRPT][3];
   auto fetch_b = [&](int k, BRegs& bb) {
@@ -187,9 +231,9 @@ __global__ __launch_bounds__(256) void k_tile3d(Op<T> op, const T* __restrict__ 
     const int kk = min(k, nz - 1);
 #pragma unroll
     for (int r = 0; r < kRPT; ++r) {
-      bb[r][0] = b[fo[r][0] + kk * pu];
-      bb[r][1] = b[fo[r][1] + kk * pv];
-      bb[r][2] = b[fo[r][2] + kk * pw];
+      bb[r][0] = buf_load<T>(rb, fo[r][0], unsigned(kk * pu) * E);
+      bb[r][1] = buf_load<T>(rb, fo[r][1], unsigned(kk * pv) * E);
+      bb[r][2] = buf_load<T>(rb, fo[r][2], unsigned(kk * pw) * E);
     }
   };
 
@@ -204,13 +248,13 @@ __global__ __launch_bounds__(256) void k_tile3d(Op<T> op, const T* __restrict__ 
   store_plane(1, k0 - 1, FA);
   store_plane(0, k0, FB);
   // planes k0+1 (FA) and k0+2 (FB), b of planes k0 (bA) and k0+1 (bB)
-  // (prefetches past the block's last plane read clamped, valid addresses:
-  // issuing them unconditionally keeps the number of loads in flight fixed,
-  // so each wait can leave the younger prefetches outstanding)
+  // (prefetches past the block's last plane re-read its last plane, a cache
+  // hit: issuing them unconditionally keeps the number of loads in flight
+  // fixed, so each wait can leave the younger prefetches outstanding)
   fetch_plane(k0 + 1, FA);
-  fetch_plane(k0 + 2, FB);
+  fetch_plane(min(k0 + 2, k1), FB);
   fetch_b(k0, bA);
-  fetch_b(k0 + 1, bB);
+  fetch_b(min(k0 + 1, k1 - 1), bB);
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kRPT; ++r) {
@@ -234,7 +278,7 @@ __global__ __launch_bounds__(256) void k_tile3d(Op<T> op, const T* __restrict__ 
     const int s = (k - k0) & 1, s1 = s ^ 1;
     store_plane(s1, k + 1, F);
     __syncthreads();
-    fetch_plane(k + 3, F);
+    fetch_plane(min(k + 3, k1), F);
     // divergence sums of plane k for cells (i0-1 .. i0+63) x (j0-1 .. j0+7)
     for (int e = threadIdx.x; e < (kTX + 1) * (kTY + 1); e += 256) {
       const int cj = e / (kTX + 1), ci = e - cj * (kTX + 1);
@@ -255,13 +299,12 @@ __global__ __launch_bounds__(256) void k_tile3d(Op<T> op, const T* __restrict__ 
         const bool okR = cell_ok(i, j, k);
         // ---- u-face (i, j, k): normal x
         {
-          const int f = fo[r][0] + k * pu;
-          if (i > 0 || unk_u0) {
+          {
             const T xf = S.u[s][jj][ii];
             T acc = T(0), d = T(0);
             T kn0 = T(1), kn1 = T(1), ky0 = T(1), ky1 = T(1), kz0 = T(1), kz1 = T(1);
             if (VARMU) {
-              if (i > 0) kn0 = op.mu[cidx(G, i - 1, j, k)];
+              kn0 = op.mu[cidx(G, max(i - 1, 0), j, k)];
               kn1 = op.mu[cidx(G, i, j, k)];
               ky0 = edge_mu<2>(op, i, j, k);
               ky1 = edge_mu<2>(op, i, j + 1, k);
@@ -281,20 +324,18 @@ __global__ __launch_bounds__(256) void k_tile3d(Op<T> op, const T* __restrict__ 
               acc += eta * (cR - cL);
               d += eta * T(cnt);
             }
-            part += tile_finish<T, MODE>(f, acc * ih2, d * ih2, xf, bc[r][0], y, omega);
-          } else {
-            y[f] = T(0);
+            part += tile_finish<T, MODE>(fo[r][0], unsigned(k * pu) * E, i > 0 || unk_u0,
+                                         acc * ih2, d * ih2, xf, bc[r][0], ry, omega);
           }
         }
         // ---- v-face (i, j, k): normal y
         {
-          const int f = fo[r][1] + k * pv;
-          if (j > 0 || unk_v0) {
+          {
             const T xf = S.v[s][jj][ii];
             T acc = T(0), d = T(0);
             T kn0 = T(1), kn1 = T(1), kx0 = T(1), kx1 = T(1), kz0 = T(1), kz1 = T(1);
             if (VARMU) {
-              if (j > 0) kn0 = op.mu[cidx(G, i, j - 1, k)];
+              kn0 = op.mu[cidx(G, i, max(j - 1, 0), k)];
               kn1 = op.mu[cidx(G, i, j, k)];
               kx0 = edge_mu<2>(op, i, j, k);
               kx1 = edge_mu<2>(op, i + 1, j, k);
@@ -314,20 +355,18 @@ __global__ __launch_bounds__(256) void k_tile3d(Op<T> op, const T* __restrict__ 
               acc += eta * (cR - cL);
               d += eta * T(cnt);
             }
-            part += tile_finish<T, MODE>(f, acc * ih2, d * ih2, xf, bc[r][1], y, omega);
-          } else {
-            y[f] = T(0);
+            part += tile_finish<T, MODE>(fo[r][1], unsigned(k * pv) * E, j > 0 || unk_v0,
+                                         acc * ih2, d * ih2, xf, bc[r][1], ry, omega);
           }
         }
         // ---- w-face (i, j, k): normal z
         {
-          const int f = fo[r][2] + k * pw;
-          if (k > 0 || unk_w0) {
+          {
             const T xf = S.w[s][jj][ii];
             T acc = T(0), d = T(0);
             T kn0 = T(1), kn1 = T(1), kx0 = T(1), kx1 = T(1), ky0 = T(1), ky1 = T(1);
             if (VARMU) {
-              if (k > 0) kn0 = op.mu[cidx(G, i, j, k - 1)];
+              kn0 = op.mu[cidx(G, i, j, max(k - 1, 0))];
               kn1 = op.mu[cidx(G, i, j, k)];
               kx0 = edge_mu<1>(op, i, j, k);
               kx1 = edge_mu<1>(op, i + 1, j, k);
@@ -346,22 +385,21 @@ __global__ __launch_bounds__(256) void k_tile3d(Op<T> op, const T* __restrict__ 
               acc += eta * (cR - cdp[r]);
               d += eta * T(cnt);
             }
-            part += tile_finish<T, MODE>(f, acc * ih2, d * ih2, xf, bc[r][2], y, omega);
-          } else {
-            y[f] = T(0);
+            part += tile_finish<T, MODE>(fo[r][2], unsigned(k * pw) * E, k > 0 || unk_w0,
+                                         acc * ih2, d * ih2, xf, bc[r][2], ry, omega);
           }
         }
         // upper boundary faces are Dirichlet faces: keep them zero
-        if (i == nx - 1) y[fo[r][0] + k * pu + 1] = T(0);
-        if (j == ny - 1) y[fo[r][1] + k * pv + nx] = T(0);
-        if (k == nz - 1) y[fo[r][2] + nz * pw] = T(0);
+        if (i == nx - 1) buf_store(T(0), ry, fo[r][0] + E, unsigned(k * pu) * E);
+        if (j == ny - 1) buf_store(T(0), ry, fo[r][1] + unsigned(nx) * E, unsigned(k * pv) * E);
+        if (k == nz - 1) buf_store(T(0), ry, fo[r][2], unsigned(nz * pw) * E);
         up[r] = S.u[s][jj][ii];
         vp[r] = S.v[s][jj][ii];
         wp[r] = S.w[s][jj][ii];
         cdp[r] = cR;
       }
     }
-    fetch_b(k + 2, bc);
+    fetch_b(min(k + 2, k1 - 1), bc);
     __syncthreads();
   };
   for (int k = k0; k < k1; k += 2) {
