@@ -124,11 +124,12 @@ typedef struct {
   long inner_iterations;  /* inner Krylov iterations summed over all solves */
   int inner_solves;
   int fallbacks;          /* learned -> MG-PCG switches inside inner solves */
-  int learned_solves;     /* inner solves started with the network.  A solve
-                             whose network fails the guards at the first
-                             application runs as plain MG-PCG; after any
-                             fallback the network stays off for the rest of
-                             the gkb_solve */
+  int learned_solves;     /* inner solves started with the network.  When the
+                             network fails a guard (descent, progress, gain)
+                             the solve restarts as plain MG-PCG from x = 0
+                             (the abandoned iterations still count in
+                             inner_iterations) and the network stays off for
+                             the rest of the gkb_solve */
   double residual;        /* final ||res||_2 / ||[g; r]||_2 (FP64), -1 if not computed */
   double error_estimate;  /* last lower-bound ratio */
   double seconds_solve;   /* wall time of the last gkb_solve */

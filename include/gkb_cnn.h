@@ -6,7 +6,7 @@
  * V = one multigrid V-cycle, rt = r - M V(r) the residual the V-cycle leaves,
  * s = RMS of rt, lambda = mean of diag(W).
  * Plain multigrid-PCG is the fallback when the network's direction fails a
- * descent or progress test.  (The paper's inner solver is any Krylov method
+ * descent, progress or energy-gain test (gkb_stats_t.learned_solves).  (The paper's inner solver is any Krylov method
  * with a swappable preconditioner, Section 3; the network itself has no
  * counterpart in the paper.)
  *

@@ -172,9 +172,14 @@ struct Inner {
   T *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *dinv = nullptr;
   T *rprev = nullptr;  // flexible CG
   PcgState* st = nullptr;
+  // captured chunks of iterations: PCG (Jacobi or MG preconditioner) and
+  // flexible CG with the network, kept apart because the learned mode falls
+  // back to plain MG-PCG
   hipGraphExec_t graph = nullptr;
   int graph_len = 0;
   int graph_mode = -1;
+  hipGraphExec_t graph_fcg = nullptr;
+  int graph_fcg_len = 0;
 };
 
 }  // namespace
@@ -410,7 +415,9 @@ void pcg_iterations(gkb_ctx* c, Inner<T>& in, int count) {
 
 template <typename T>
 int ensure_graph(gkb_ctx* c, Inner<T>& in, int count) {
-  if (in.graph && in.graph_len == count && in.graph_mode == c->opt.inner) return GKB_OK;
+  // the PCG iteration depends only on the preconditioner (Jacobi or V-cycle)
+  const int key = c->opt.inner == GKB_INNER_JACOBI ? GKB_INNER_JACOBI : GKB_INNER_MG;
+  if (in.graph && in.graph_len == count && in.graph_mode == key) return GKB_OK;
   if (in.graph) {
     (void)hipGraphExecDestroy(in.graph);
     in.graph = nullptr;
@@ -422,7 +429,7 @@ int ensure_graph(gkb_ctx* c, Inner<T>& in, int count) {
   HIPCK(hipGraphInstantiate(&in.graph, gr, nullptr, nullptr, 0));
   (void)hipGraphDestroy(gr);
   in.graph_len = count;
-  in.graph_mode = c->opt.inner;
+  in.graph_mode = key;
   return GKB_OK;
 }
 
@@ -1240,6 +1247,8 @@ void gkb_destroy(gkb_ctx* c) {
   if (c->cs) (void)hipStreamSynchronize(c->cs);
   if (c->in64.graph) (void)hipGraphExecDestroy(c->in64.graph);
   if (c->in32.graph) (void)hipGraphExecDestroy(c->in32.graph);
+  if (c->in64.graph_fcg) (void)hipGraphExecDestroy(c->in64.graph_fcg);
+  if (c->in32.graph_fcg) (void)hipGraphExecDestroy(c->in32.graph_fcg);
   if (c->learned) learned_destroy(c);
   c->mem.release();
   if (c->hbuf) (void)hipHostFree(c->hbuf);

@@ -8,8 +8,8 @@ struct gkb_ctx;
 struct Learned;
 
 namespace {
-// learned_solve's return value when the network failed its guards at the
-// first application: the caller runs the plain MG-PCG solve instead
+// learned_solve's return value when the network failed one of its guards:
+// the caller runs the plain MG-PCG solve (from x = 0) instead
 constexpr int kLearnedDeclined = 2;
 bool learned_enabled(Learned* L);
 bool learned_capturing(Learned* L);

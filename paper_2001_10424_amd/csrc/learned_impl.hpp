@@ -432,26 +432,41 @@ int learned_solve(gkb_ctx* c, const double* f, double* x_out, double tol, int* i
   }
   const int chunk = std::max(1, c->opt.check_every);
   if (c->opt.use_graphs) {
-    if (!(in.graph && in.graph_len == chunk && in.graph_mode == GKB_INNER_LEARNED)) {
-      if (in.graph) (void)hipGraphExecDestroy(in.graph);
-      in.graph = nullptr;
+    if (!(in.graph_fcg && in.graph_fcg_len == chunk)) {
+      if (in.graph_fcg) (void)hipGraphExecDestroy(in.graph_fcg);
+      in.graph_fcg = nullptr;
       hipGraph_t gr;
       HIPCK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
       fcg_iterations<T>(c, in, chunk);
       HIPCK(hipStreamEndCapture(s, &gr));
-      HIPCK(hipGraphInstantiate(&in.graph, gr, nullptr, nullptr, 0));
+      HIPCK(hipGraphInstantiate(&in.graph_fcg, gr, nullptr, nullptr, 0));
       (void)hipGraphDestroy(gr);
-      in.graph_len = chunk;
-      in.graph_mode = GKB_INNER_LEARNED;
+      in.graph_fcg_len = chunk;
     }
   }
   for (;;) {
-    if (c->opt.use_graphs) HIPCK(hipGraphLaunch(in.graph, s));
+    if (c->opt.use_graphs) HIPCK(hipGraphLaunch(in.graph_fcg, s));
     else fcg_iterations<T>(c, in, chunk);
     HIPCK(hipMemcpyAsync(c->hbuf, in.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
     HIPCK(hipStreamSynchronize(s));
     std::memcpy(&hs, c->hbuf, sizeof(PcgState));
     if (hs.done) break;
+    if (hs.fallback && !hs.nonfinite) {
+      // the network failed a guard during the solve: its flexible-CG iterates
+      // are dropped and plain MG-PCG solves from scratch (a direction the
+      // network spoiled can slow the rest of a flexible-CG solve a lot)
+      c->stats.inner_iterations += hs.it;
+      c->stats.learned_solves += 1;
+      c->stats.fallbacks += hs.fallbacks;
+      L->gain_sum += hs.gain_sum;
+      L->gain_n += hs.gain_n;
+      c->stats.learned_gain = L->gain_n ? L->gain_sum / L->gain_n : -1.0;
+      L->off = true;
+      if (std::getenv("GKB_DEBUG"))
+        std::fprintf(stderr, "learned solve abandoned at it %d (fallback at %d, reason %d)\n", hs.it,
+                     hs.fb_it, hs.fb_reason);
+      return kLearnedDeclined;
+    }
   }
   k_cast<T, double><<<vb, kBlock, 0, s>>>(n, in.x, x_out);
   if (std::getenv("GKB_DEBUG"))
@@ -557,10 +572,11 @@ int gkb_attach_cnn(gkb_ctx* c, gkb_cnn* net) {
     CK(cnn_reserve(net, c->g.n_cells));
   }
   c->learned->net = net;
-  if (c->in32.graph) (void)hipGraphExecDestroy(c->in32.graph);
-  if (c->in64.graph) (void)hipGraphExecDestroy(c->in64.graph);
-  c->in32.graph = nullptr;
-  c->in64.graph = nullptr;
+  // the flexible-CG graphs hold the network's buffers; the PCG graphs do not
+  if (c->in32.graph_fcg) (void)hipGraphExecDestroy(c->in32.graph_fcg);
+  if (c->in64.graph_fcg) (void)hipGraphExecDestroy(c->in64.graph_fcg);
+  c->in32.graph_fcg = nullptr;
+  c->in64.graph_fcg = nullptr;
   return GKB_OK;
 }
 

@@ -226,3 +226,33 @@ def test_sabotaged_network_falls_back_and_converges():
     assert nr[0] <= 1e-8 * nr[3]
     assert info["fallbacks"] > 0
     s.close()
+
+
+def test_abandoned_learned_solve_restarts_as_plain_mg_pcg():
+    """A network that passes its first application (so the flexible-CG
+    iterations are captured in a graph) and later stalls: the solve is
+    abandoned, plain MG-PCG takes over for it and for the rest of the
+    gkb_solve, and the answer is bitwise the one of inner = "mg" (the
+    learned mode's fallback must not replay the flexible-CG graph)."""
+    _say("abandoned learned solve")
+    gk = _gk()
+    net = gk.CNN(3, (4, 3), seed=0)
+    p = np.zeros(net.n_params, np.float32)
+    for a in range(3):  # identity map of the three residual channels, centre tap
+        p[13 * 4 * 3 + a * 3 + a] = 1.0
+    net.params = p
+    pr = _small_problem(7, n=48)
+    out = {}
+    for inner in ("mg", "learned"):
+        s = _solver(gk, pr, inner=inner, inner_tol=1e-3)
+        if inner == "learned":
+            s.attach_cnn(net)
+        w, pp, info = s.solve(_dev(pr.g), _dev(pr.r), tol=1e-2, delay=2)
+        out[inner] = (w.cpu().numpy(), info)
+        s.close()
+    (wm, im), (wl, il) = out["mg"], out["learned"]
+    print("gain", il["learned_gain"], "inner", im["inner_iterations"], il["inner_iterations"], flush=True)
+    assert il["learned_solves"] == 1 and il["fallbacks"] >= 1 and il["learned_gain"] > 0.05
+    assert np.array_equal(wm, wl)
+    assert il["inner_iterations"] > im["inner_iterations"]
+    assert il["outer_iterations"] == im["outer_iterations"] and il["sweeps"] == im["sweeps"]
