@@ -31,7 +31,7 @@ def _gk():
 # as timed by bench.py
 BENCH_MODES = {
     "fp64_mg": dict(precision="fp64", inner="mg", inner_tol=1e-3, tol=1e-2, delay=2),
-    "mixed_mg": dict(precision="mixed", inner="mg", inner_tol=1e-3, tol=1e-2, delay=2),
+    "mixed_mg": dict(precision="mixed", inner="mg", inner_tol=3e-3, tol=3e-2, delay=2),
     "fp64_gkb1": dict(precision="fp64", inner="mg", inner_tol=1e-10, tol=1e-9, delay=5),
     "fp64_mg_hybrid": dict(precision="fp64", inner="mg", inner_tol=3e-4, tol=3e-3, delay=2,
                            smoother="hybrid", nu_pre=1, nu_post=1),
@@ -146,4 +146,26 @@ def test_varvisc_reduced_solve(dim, n, mu_seed):
     _, _, nr = oracle.saddle_residual(pr.grid, pr.g, pr.r, w.cpu().numpy(), p.cpu().numpy(),
                                       mu=pr.mu)
     assert nr[0] <= 1e-8 * nr[3]
+    s.close()
+
+
+@pytest.mark.parametrize("dim,n,mu_seed", [(2, 256, 7), (3, 192, 8)])
+def test_varvisc_full_size_solve_hybrid(dim, n, mu_seed):
+    """The variable-viscosity workloads (log-normal mu, contrast 1e3, eta =
+    1e3) at full size with FP32 inner MG-PCG on the hybrid face + edge
+    smoother (point-Jacobi multigrid needs thousands of iterations per inner
+    solve here): FP64 residual <= 1e-8 by the oracle."""
+    _say("varvisc full solve hybrid", dim, n)
+    gk = _gk()
+    pr = P.stokes_problem(dim, n, seed=10000, eta=1e3, mu_seed=mu_seed)
+    s = gk.Solver(pr.grid, pr.mu, pr.eta, precision="mixed", inner="mg", smoother="hybrid",
+                  nu_pre=1, nu_post=1, inner_tol=3e-4, inner_maxit=20000, maxit=200,
+                  refine_tol=1e-8, max_sweeps=30)
+    w, p, info = s.solve(_dev(pr.g), _dev(pr.r), tol=3e-3, delay=2)
+    print("[case] sweeps", info["sweeps"], "K", info["outer_iterations"], "inner",
+          info["inner_iterations"], flush=True)
+    _, _, nr = oracle.saddle_residual(pr.grid, pr.g, pr.r, w.cpu().numpy(), p.cpu().numpy(),
+                                      mu=pr.mu)
+    assert nr[0] <= 1e-8 * nr[3]
+    assert info["mg_levels"] == (6 if dim == 3 else 5)
     s.close()
