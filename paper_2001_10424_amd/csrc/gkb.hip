@@ -162,6 +162,9 @@ struct Level {
   FaceLaunch fl;
   // hybrid smoother: edge potential and 1/diag(C^T W C) (nullptr: Jacobi only)
   T *psi = nullptr, *edinv = nullptr;
+  // 1/diag(M_l) on the coarse levels that smooth: the restriction into the
+  // level writes its first sweep from a zero guess in the same pass
+  T* dinv = nullptr;
   double omega_e = 0.0;
 };
 
@@ -292,9 +295,11 @@ void edge_step(gkb_ctx* c, Level<T>& L, const T* b, T* x, const PcgState* st) {
   }
 }
 
+// first_done: the first pre-smoothing sweep from a zero guess is already in
+// its output buffer (written by the restriction into this level)
 template <typename T>
 void vcycle(gkb_ctx* c, Inner<T>& in, int l, const T* b, T* x, double* dot_partial,
-            const PcgState* st) {
+            const PcgState* st, bool first_done = false) {
   Level<T>& L = in.lv[l];
   hipStream_t s = c->cs;
   if (l == c->L - 1) {
@@ -315,7 +320,7 @@ void vcycle(gkb_ctx* c, Inner<T>& in, int l, const T* b, T* x, double* dot_parti
   if (n1 > 0) {
     ++k;
     T* o = dst(k);
-    face_op<T, kJacobi0>(c, L.op, L.fl, nullptr, b, o, om, nullptr, st);
+    if (!first_done) face_op<T, kJacobi0>(c, L.op, L.fl, nullptr, b, o, om, nullptr, st);
     if (hybrid) edge_step<T>(c, L, b, o, st);
     cur = o;
     for (int i = 1; i < n1; ++i) {
@@ -328,15 +333,17 @@ void vcycle(gkb_ctx* c, Inner<T>& in, int l, const T* b, T* x, double* dot_parti
   }
   Level<T>& Lc = in.lv[l + 1];
   const dim3 tg = transfer_grid(Lc.g);
-  if (cur) {
-    face_op<T, kResid>(c, L.op, L.fl, cur, b, L.rb, T(0), nullptr, st);
-    if (L.g.dim == 2) k_restrict<T, 2><<<tg, kBlock, 0, s>>>(L.g, Lc.g, L.rb, Lc.b, st);
-    else k_restrict<T, 3><<<tg, kBlock, 0, s>>>(L.g, Lc.g, L.rb, Lc.b, st);
-  } else {
-    if (L.g.dim == 2) k_restrict<T, 2><<<tg, kBlock, 0, s>>>(L.g, Lc.g, b, Lc.b, st);
-    else k_restrict<T, 3><<<tg, kBlock, 0, s>>>(L.g, Lc.g, b, Lc.b, st);
-  }
-  vcycle<T>(c, in, l + 1, Lc.b, Lc.x, nullptr, st);
+  // the coarse level's first sweep (x = omega D^-1 b) goes where its V-cycle
+  // puts the first pre-smoothing result
+  T* x0c = (n1 > 0 && Lc.dinv) ? (((tot - 1) % 2 == 0) ? Lc.x : Lc.t) : nullptr;
+  const T omc = T(Lc.omega);
+  const T* rsrc = cur ? L.rb : b;
+  if (cur) face_op<T, kResid>(c, L.op, L.fl, cur, b, L.rb, T(0), nullptr, st);
+  if (L.g.dim == 2)
+    k_restrict<T, 2><<<tg, kBlock, 0, s>>>(L.g, Lc.g, rsrc, Lc.b, st, Lc.dinv, omc, x0c);
+  else
+    k_restrict<T, 3><<<tg, kBlock, 0, s>>>(L.g, Lc.g, rsrc, Lc.b, st, Lc.dinv, omc, x0c);
+  vcycle<T>(c, in, l + 1, Lc.b, Lc.x, nullptr, st, x0c != nullptr);
   // prolongate into the current iterate (or into a zeroed x when no pre-smoothing)
   T* it = const_cast<T*>(cur);
   if (!it) {
@@ -826,6 +833,14 @@ int build_inner(gkb_ctx* c, Inner<T>& in, const std::vector<Coef<T>>& coef) {
     }
     CK(c->mem.arr(&lv.t, m));
     CK(c->mem.arr(&lv.rb, m));
+    if (l >= 1 && l < L - 1) {
+      CK(c->mem.arr(&lv.dinv, m));
+      face_op<T, kDiag>(c, lv.op, lv.fl, nullptr, nullptr, lv.dinv, T(0), nullptr, nullptr);
+      std::vector<T> dh(m);
+      CK(copy_sync(c, dh.data(), lv.dinv, m * sizeof(T), hipMemcpyDeviceToHost));
+      for (auto& v : dh) v = v != T(0) ? T(1) / v : T(0);
+      CK(copy_sync(c, lv.dinv, dh.data(), m * sizeof(T), hipMemcpyHostToDevice));
+    }
     if (l < L - 1 && l < (int)c->edinv_h.size() && !c->edinv_h[l].empty()) {
       const std::vector<double>& dh = c->edinv_h[l];
       CK(c->mem.arr(&lv.psi, dh.size()));

@@ -512,10 +512,13 @@ __global__ __launch_bounds__(kBlock) void k_pcg_p(int n, const PcgState* __restr
 // Restriction of face residuals, full weighting: coarse face = (1/2^d) *
 // sum over the fine faces it covers, normal neighbours weighted 1/2
 // (transpose of the prolongation below divided by 2^d).
+// x0c (optional): the coarse level's first smoothing sweep from a zero
+// guess, x0c = omega_c dinv_c bc, written in the same pass
 template <typename T, int DIM, int C>
 __device__ __forceinline__ void restrict_face(const Grid& Gf, const Grid& Gc,
                                               const T* __restrict__ rf, T* __restrict__ bc,
-                                              const PcgState* st, int idx, int k) {
+                                              const T* __restrict__ dinv_c, T omega_c,
+                                              T* __restrict__ x0c, int idx, int k) {
   const int e0 = Gc.ext[C][0], e1 = Gc.ext[C][1];
   if (idx >= e0 * e1 || k >= Gc.ext[C][2]) return;
   const int j = idx / e0, i = idx - j * e0;
@@ -523,6 +526,7 @@ __device__ __forceinline__ void restrict_face(const Grid& Gf, const Grid& Gc,
   const int f = fidx<C>(Gc, i, j, k);
   if (!unk<C>(Gc, P[C])) {
     bc[f] = T(0);
+    if (x0c) x0c[f] = T(0);
     return;
   }
   T acc = T(0);
@@ -546,19 +550,23 @@ __device__ __forceinline__ void restrict_face(const Grid& Gf, const Grid& Gc,
         acc += wn * ldm<C>(Gf, rf, Q[0], Q[1], Q[2]);
       }
   }
-  bc[f] = acc * T(DIM == 3 ? 0.125 : 0.25);
+  const T v = acc * T(DIM == 3 ? 0.125 : 0.25);
+  bc[f] = v;
+  if (x0c) x0c[f] = omega_c * dinv_c[f] * v;
 }
 
 template <typename T, int DIM>
 __global__ __launch_bounds__(kBlock) void k_restrict(Grid Gf, Grid Gc, const T* __restrict__ rf,
-                                                     T* __restrict__ bc, const PcgState* st) {
+                                                     T* __restrict__ bc, const PcgState* st,
+                                                     const T* __restrict__ dinv_c = nullptr,
+                                                     T omega_c = T(0), T* __restrict__ x0c = nullptr) {
   if (st && st->done) return;
   const int c = blockIdx.z / Gc.nze;
   const int k = blockIdx.z - c * Gc.nze;
   const int idx = blockIdx.x * kBlock + threadIdx.x;
-  if (c == 0) restrict_face<T, DIM, 0>(Gf, Gc, rf, bc, st, idx, k);
-  else if (c == 1) restrict_face<T, DIM, 1>(Gf, Gc, rf, bc, st, idx, k);
-  else if (DIM == 3) restrict_face<T, DIM, 2>(Gf, Gc, rf, bc, st, idx, k);
+  if (c == 0) restrict_face<T, DIM, 0>(Gf, Gc, rf, bc, dinv_c, omega_c, x0c, idx, k);
+  else if (c == 1) restrict_face<T, DIM, 1>(Gf, Gc, rf, bc, dinv_c, omega_c, x0c, idx, k);
+  else if (DIM == 3) restrict_face<T, DIM, 2>(Gf, Gc, rf, bc, dinv_c, omega_c, x0c, idx, k);
 }
 
 // Prolongation + correction: fine faces coinciding with a coarse face take
