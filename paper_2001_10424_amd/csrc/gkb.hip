@@ -160,8 +160,8 @@ struct Level {
   T *b = nullptr, *x = nullptr, *t = nullptr, *rb = nullptr;
   double omega = 0.8;
   FaceLaunch fl;
-  // hybrid smoother: edge potential and 1/diag(C^T W C) (nullptr: Jacobi only)
-  T *psi = nullptr, *edinv = nullptr;
+  // hybrid smoother: 1/diag(C^T W C) on the edges (nullptr: Jacobi only)
+  T* edinv = nullptr;
   // 1/diag(M_l) on the coarse levels that smooth: the restriction into the
   // level writes its first sweep from a zero guess in the same pass
   T* dinv = nullptr;
@@ -286,13 +286,8 @@ void edge_step(gkb_ctx* c, Level<T>& L, const T* b, T* x, const PcgState* st) {
   hipStream_t s = c->cs;
   face_op<T, kResid>(c, L.op, L.fl, x, b, L.rb, T(0), nullptr, st);
   const dim3 cg = cell_grid(L.g);
-  if (L.g.dim == 2) {
-    k_edge_ct<T, 2><<<cg, kBlock, 0, s>>>(L.g, L.rb, L.edinv, T(L.omega_e), L.psi, st);
-    k_curl_add<T, 2><<<cg, kBlock, 0, s>>>(L.g, L.psi, x, st);
-  } else {
-    k_edge_ct<T, 3><<<cg, kBlock, 0, s>>>(L.g, L.rb, L.edinv, T(L.omega_e), L.psi, st);
-    k_curl_add<T, 3><<<cg, kBlock, 0, s>>>(L.g, L.psi, x, st);
-  }
+  if (L.g.dim == 2) k_edge_smooth<T, 2><<<cg, kBlock, 0, s>>>(L.g, L.rb, L.edinv, T(L.omega_e), x, st);
+  else k_edge_smooth<T, 3><<<cg, kBlock, 0, s>>>(L.g, L.rb, L.edinv, T(L.omega_e), x, st);
 }
 
 // first_done: the first pre-smoothing sweep from a zero guess is already in
@@ -312,7 +307,7 @@ void vcycle(gkb_ctx* c, Inner<T>& in, int l, const T* b, T* x, double* dot_parti
   }
   const int n1 = c->opt.nu_pre, n2 = c->opt.nu_post, tot = n1 + n2;
   const T om = T(L.omega);
-  const bool hybrid = L.psi != nullptr;
+  const bool hybrid = L.edinv != nullptr;
   // sweep k writes x when (tot - k) is even, else t
   auto dst = [&](int k) { return ((tot - k) % 2 == 0) ? x : L.t; };
   const T* cur = nullptr;
@@ -843,7 +838,6 @@ int build_inner(gkb_ctx* c, Inner<T>& in, const std::vector<Coef<T>>& coef) {
     }
     if (l < L - 1 && l < (int)c->edinv_h.size() && !c->edinv_h[l].empty()) {
       const std::vector<double>& dh = c->edinv_h[l];
-      CK(c->mem.arr(&lv.psi, dh.size()));
       CK(upload<T>(c, dh, &lv.edinv));
       lv.omega_e = c->omega_e[l];
     }

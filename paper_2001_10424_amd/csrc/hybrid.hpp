@@ -125,6 +125,63 @@ __global__ __launch_bounds__(kBlock) void k_curl_add(Grid G, const T* __restrict
     x[fidx<2>(G, i, j, k)] += pt(G, py, i + 1, j, k) - sy - pt(G, px, i, j + 1, k) + sx;
 }
 
+// psi_A = omega dinv_A (C^T r)_A at point (i, j, k) >= 0; 0 beyond the point
+// grid or in a DIRICHLET wall
+template <typename T, int DIM, int A>
+__device__ __forceinline__ T edge_psi(const Grid& G, const T* __restrict__ r,
+                                      const T* __restrict__ dinv, T omega, int i, int j, int k) {
+  if (i >= G.n[0] || j >= G.n[1] || k >= G.n[2] || edge_in_wall<DIM>(G, A, i, j, k)) return T(0);
+  T t;
+  if (DIM == 2)
+    t = face_at<0>(G, r, i, j - 1, 0) - face_at<0>(G, r, i, j, 0) - face_at<1>(G, r, i - 1, j, 0) +
+        face_at<1>(G, r, i, j, 0);
+  else if (A == 0)
+    t = face_at<1>(G, r, i, j, k - 1) - face_at<1>(G, r, i, j, k) - face_at<2>(G, r, i, j - 1, k) +
+        face_at<2>(G, r, i, j, k);
+  else if (A == 1)
+    t = face_at<0>(G, r, i, j, k) - face_at<0>(G, r, i, j, k - 1) + face_at<2>(G, r, i - 1, j, k) -
+        face_at<2>(G, r, i, j, k);
+  else
+    t = face_at<0>(G, r, i, j - 1, k) - face_at<0>(G, r, i, j, k) - face_at<1>(G, r, i - 1, j, k) +
+        face_at<1>(G, r, i, j, k);
+  const long p = ((long)k * G.n[1] + j) * G.n[0] + i;
+  return omega * dinv[(long)A * G.n_cells + p] * t;
+}
+
+// The edge half of the hybrid smoother in one pass: x += C omega D_e^-1 C^T r
+// on the lower faces of every cell.  Each point evaluates the edge values its
+// three faces need (nine in 3D, three in 2D) straight from r; neighbouring
+// points share those reads through the caches, and the edge field is never
+// stored.
+template <typename T, int DIM>
+__global__ __launch_bounds__(kBlock) void k_edge_smooth(Grid G, const T* __restrict__ r,
+                                                        const T* __restrict__ dinv, T omega,
+                                                        T* __restrict__ x, const PcgState* st) {
+  if (st && st->done) return;
+  const int k = blockIdx.z;
+  const int idx = blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= G.n[0] * G.n[1]) return;
+  const int j = idx / G.n[0], i = idx - j * G.n[0];
+  if (DIM == 2) {
+    const T s = edge_psi<T, 2, 0>(G, r, dinv, omega, i, j, 0);
+    if (unk<0>(G, i)) x[fidx<0>(G, i, j, 0)] += edge_psi<T, 2, 0>(G, r, dinv, omega, i, j + 1, 0) - s;
+    if (unk<1>(G, j)) x[fidx<1>(G, i, j, 0)] += s - edge_psi<T, 2, 0>(G, r, dinv, omega, i + 1, j, 0);
+    return;
+  }
+  const T sx = edge_psi<T, 3, 0>(G, r, dinv, omega, i, j, k);
+  const T sy = edge_psi<T, 3, 1>(G, r, dinv, omega, i, j, k);
+  const T sz = edge_psi<T, 3, 2>(G, r, dinv, omega, i, j, k);
+  if (unk<0>(G, i))
+    x[fidx<0>(G, i, j, k)] += edge_psi<T, 3, 2>(G, r, dinv, omega, i, j + 1, k) - sz -
+                              edge_psi<T, 3, 1>(G, r, dinv, omega, i, j, k + 1) + sy;
+  if (unk<1>(G, j))
+    x[fidx<1>(G, i, j, k)] += edge_psi<T, 3, 0>(G, r, dinv, omega, i, j, k + 1) - sx -
+                              edge_psi<T, 3, 2>(G, r, dinv, omega, i + 1, j, k) + sz;
+  if (unk<2>(G, k))
+    x[fidx<2>(G, i, j, k)] += edge_psi<T, 3, 1>(G, r, dinv, omega, i + 1, j, k) - sy -
+                              edge_psi<T, 3, 0>(G, r, dinv, omega, i, j + 1, k) + sx;
+}
+
 // probe for diag(C^T W C): psi = 1 on the edges of component a whose point is
 // congruent to (cx, cy, cz) modulo 3 and not in a wall, 0 elsewhere.  Two
 // such edges are three points apart along some axis, so their curls touch
