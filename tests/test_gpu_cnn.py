@@ -256,3 +256,21 @@ def test_abandoned_learned_solve_restarts_as_plain_mg_pcg():
     assert np.array_equal(wm, wl)
     assert il["inner_iterations"] > im["inner_iterations"]
     assert il["outer_iterations"] == im["outer_iterations"] and il["sweeps"] == im["sweeps"]
+
+
+def test_corrupted_checkpoint_is_rejected(tmp_path):
+    _say("corrupted checkpoint")
+    gk = _gk()
+    net = gk.CNN(3, (4, 8, 3), seed=9)
+    good = str(tmp_path / "w.bin")
+    net.save(good)
+    raw = open(good, "rb").read()
+    bad_magic = str(tmp_path / "magic.bin")
+    with open(bad_magic, "wb") as f:
+        f.write(b"NOTACNN!" + raw[8:])
+    short = str(tmp_path / "short.bin")
+    with open(short, "wb") as f:
+        f.write(raw[: len(raw) // 2])
+    for path in (bad_magic, short, str(tmp_path / "missing.bin")):
+        with pytest.raises(RuntimeError):
+            gk.CNN.load(path)

@@ -197,3 +197,40 @@ def test_deterministic_bitwise():
     assert bool((w1 == w2).all()) and bool((p1 == p2).all())
     assert i1["inner_iterations"] == i2["inner_iterations"]
     s.close()
+
+
+def test_workspace_cap_reports_enomem():
+    _say("workspace cap")
+    gk = _gk()
+    g = P.Grid(3, (32, 32, 32), 1 / 32, (D,) * 6, 0)
+    with pytest.raises(RuntimeError, match="gkb_setup"):
+        gk.Solver(g, None, 1e3, inner="mg", max_workspace_bytes=1 << 20)
+    s = gk.Solver(g, None, 1e3, inner="mg", max_workspace_bytes=1 << 30)
+    assert 0 < s.stats()["workspace_bytes"] <= 1 << 30
+    s.close()
+
+
+@pytest.mark.parametrize("name,grid,prec,smoother", [
+    ("3d_tiled_pin", P.Grid(3, (16, 16, 16), 1 / 16, (D,) * 6, 0), "mixed", "jacobi"),
+    ("2d_outflow", P.Grid(2, (32, 8, 1), 1 / 8, (D, N, D, D, D, D), -1), "fp64", "hybrid"),
+    ("3d_hybrid", P.Grid(3, (16, 8, 16), 1 / 8, (D,) * 6, 0), "fp64", "hybrid"),
+])
+def test_outputs_fully_written(name, grid, prec, smoother):
+    """Output buffers poisoned with NaN before the solve hold finite values
+    everywhere afterwards: the non-unknown faces and the pinned cell as 0."""
+    _say("outputs written", name)
+    torch = _torch()
+    gk = _gk()
+    pr_g = P.random_vector(grid, 5)
+    s = gk.Solver(grid, None, 1e2, inner="mg", precision=prec, smoother=smoother,
+                  refine_tol=1e-8, max_sweeps=12, inner_tol=1e-6)
+    w = torch.full((grid.m_full,), float("nan"), dtype=torch.float64, device="cuda")
+    p = torch.full((grid.n_cells,), float("nan"), dtype=torch.float64, device="cuda")
+    s.solve(_dev(pr_g), torch.zeros(grid.n_cells, dtype=torch.float64, device="cuda"),
+            tol=1e-6, w=w, p=p)
+    wn, pn = w.cpu().numpy(), p.cpu().numpy()
+    assert np.isfinite(wn).all() and np.isfinite(pn).all()
+    assert np.all(wn[grid.face_mask() == 0] == 0.0)
+    if grid.pin >= 0:
+        assert pn[grid.pin] == 0.0
+    s.close()
