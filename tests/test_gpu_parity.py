@@ -234,3 +234,20 @@ def test_outputs_fully_written(name, grid, prec, smoother):
     if grid.pin >= 0:
         assert pn[grid.pin] == 0.0
     s.close()
+
+
+@pytest.mark.parametrize("dim,n", [(2, 3), (3, 2)])
+def test_run_past_exhaustion_on_tiny_grids(dim, n):
+    """Without a stopping tolerance (tol <= 0) on grids with a handful of
+    pressure unknowns, GKB runs three times as many steps as there are
+    unknowns, past the exhaustion of the Krylov space (where breakdown or
+    repeated converged values end or continue the recurrence): the same
+    status and K as the oracle, the same iterates, and the exact solution."""
+    _say("past exhaustion", dim, n)
+    pr = P.stokes_problem(dim, n, seed=4, eta=10.0)
+    n_unknown = pr.grid.n_cells - 1
+    w, p, info, ref = _gkb_pair(pr, 0.0, 3 * n_unknown)
+    assert info["status"] == ref["status"] and info["iterations"] == ref["K"]
+    assert _rel(w, ref["w"]) <= 1e-10 and _rel(p, ref["p"]) <= 1e-10
+    _, _, nr = oracle.saddle_residual(pr.grid, pr.g, pr.r, w, p)
+    assert nr[0] <= 1e-10 * nr[3]
