@@ -120,6 +120,37 @@ __device__ __forceinline__ double tile_finish(unsigned voff, unsigned soff, bool
   return part;
 }
 
+// Constant-viscosity variant of tile_finish: mx = (M x) at the face and sc
+// the hoisted diagonal scale (omega / D for the Jacobi modes, 1 / D for
+// kDinvM, unused otherwise).
+template <typename T, int MODE>
+__device__ __forceinline__ double tile_out(unsigned voff, unsigned soff, bool unk, T mx, T sc,
+                                           T xf, T bf, __amdgpu_buffer_rsrc_t ry) {
+  double part = 0.0;
+  T out;
+  if (MODE == kApply || MODE == kApplyDot) {
+    out = unk ? mx : T(0);
+    if (MODE == kApplyDot) part = double(xf) * double(out);
+  } else if (MODE == kJacobi || MODE == kJacobiDot) {
+    out = unk ? xf + (bf - mx) * sc : T(0);
+    if (MODE == kJacobiDot) part = double(bf) * double(out);
+  } else if (MODE == kResid || MODE == kResidDot) {
+    out = unk ? bf - mx : T(0);
+    if (MODE == kResidDot) part = double(out) * double(out);
+  } else {  // kDinvM
+    out = unk ? mx * sc : T(0);
+    part = double(out) * double(out);
+  }
+  buf_store(out, ry, voff, soff);
+  return part;
+}
+
+// diagonal count of one axis of the viscous stencil: an in-array neighbour
+// counts 1, a DIRICHLET wall across the face (mirror ghost) 2, else 0
+__device__ __forceinline__ int axis_count(bool lo_in, bool hi_in, bool lo_wall, bool hi_wall) {
+  return (lo_in ? 1 : (lo_wall ? 2 : 0)) + (hi_in ? 1 : (hi_wall ? 2 : 0));
+}
+
 // FINE only separates the finest-grid launches from the coarse-level ones in
 // kernel traces; the code is the same.
 //
@@ -166,11 +197,14 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
   const unsigned bytes = unsigned(G.m_full) * E;
   const __amdgpu_buffer_rsrc_t rx = buf_rsrc(x, bytes), ry = buf_rsrc(y, bytes);
   const __amdgpu_buffer_rsrc_t rb = reads_b<MODE>() ? buf_rsrc(b, bytes) : rx;
+  // w-array offset relative to the v array (same in-plane index: both are
+  // nx wide), added to the uniform part of a w access
+  const unsigned dw = unsigned(G.off[2] - G.off[1]) * E;
 
   // staged halo elements of this thread: in-plane byte offset (clamped) and
   // validity bits (u, v, w per element), fixed for the whole block
   constexpr int kPer = (kLX * kLY + 255) / 256;
-  unsigned hu[kPer], hv[kPer], hw[kPer];
+  unsigned hu[kPer], hv[kPer];
   unsigned hmask = 0;
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
@@ -180,8 +214,10 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
     const bool in = e < kLX * kLY && j >= 0 && j < ny && i >= 0 && i < nx;
     const bool ou = in && (i > 0 || unk_u0), ov = in && (j > 0 || unk_v0);
     hu[q] = unsigned(G.off[0] + (ou ? j * G.ext[0][0] + i : 0)) * E;
-    hv[q] = unsigned(G.off[1] + (ov ? j * G.ext[1][0] + i : 0)) * E;
-    hw[q] = unsigned(G.off[2] + (in ? j * G.ext[2][0] + i : 0)) * E;
+    // v and w share the in-plane index (both arrays are nx wide): the w
+    // offset is the v offset + dw; non-unknown v faces are masked at the
+    // LDS store, so the v offset is clamped only outside the grid
+    hv[q] = unsigned(G.off[1] + (in ? j * G.ext[1][0] + i : 0)) * E;
     hmask |= (ou ? 1u : 0u) << (3 * q);
     hmask |= (ov ? 2u : 0u) << (3 * q);
     hmask |= (in ? 4u : 0u) << (3 * q);
@@ -193,7 +229,7 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
     for (int q = 0; q < kPer; ++q) {
       F[0][q] = buf_load<T>(rx, hu[q], unsigned(kk * pu) * E);
       F[1][q] = buf_load<T>(rx, hv[q], unsigned(kk * pv) * E);
-      F[2][q] = buf_load<T>(rx, hw[q], unsigned(kk * pw) * E);
+      F[2][q] = buf_load<T>(rx, hv[q], unsigned(kk * pw) * E + dw);
     }
   };
   auto store_plane = [&](int s, int k, const FRegs& F) {
@@ -215,15 +251,15 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
     return i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz && cidx(G, i, j, k) != G.pin;
   };
 
-  // this thread's faces: in-plane byte offset of u, v, w (clamped when outside)
-  unsigned fo[kRPT][3];
+  // this thread's faces: in-plane byte offset of u and v (w: v + dw), clamped
+  // when outside
+  unsigned fo[kRPT][2];
 #pragma unroll
   for (int r = 0; r < kRPT; ++r) {
     const int i = i0 + tx, j = j0 + ty + r * kTYT;
     const bool in = i < nx && j < ny;
     fo[r][0] = unsigned(G.off[0] + (in ? j * G.ext[0][0] + i : 0)) * E;
     fo[r][1] = unsigned(G.off[1] + (in ? j * G.ext[1][0] + i : 0)) * E;
-    fo[r][2] = unsigned(G.off[2] + (in ? j * G.ext[2][0] + i : 0)) * E;
   }
   typedef T BRegs[kRPT][3];
   auto fetch_b = [&](int k, BRegs& bb) {
@@ -233,9 +269,70 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
     for (int r = 0; r < kRPT; ++r) {
       bb[r][0] = buf_load<T>(rb, fo[r][0], unsigned(kk * pu) * E);
       bb[r][1] = buf_load<T>(rb, fo[r][1], unsigned(kk * pv) * E);
-      bb[r][2] = buf_load<T>(rb, fo[r][2], unsigned(kk * pw) * E);
+      bb[r][2] = buf_load<T>(rb, fo[r][1], unsigned(kk * pw) * E + dw);
     }
   };
+
+  // pinned cell (pk = -2: none)
+  const int nxy = nx * ny;
+  const int pk = G.pin >= 0 ? G.pin / nxy : -2;
+  const int pj = G.pin >= 0 ? (G.pin - pk * nxy) / nx : -3;
+  const int pi = G.pin >= 0 ? G.pin - pk * nxy - pj * nx : -3;
+
+  // Constant viscosity: the neighbours outside the array and the
+  // non-unknown faces are zeros in LDS and in the z registers, so the
+  // off-diagonal part of every face is the plain weighted sum of its six
+  // neighbours; the diagonal (viscous count + eta x number of valid adjacent
+  // cells) changes with z only on the first and last plane and next to the
+  // pinned cell.  dv: viscous diagonal count, sc: omega / D (Jacobi modes)
+  // or 1 / D, for plane k, or (bulk) for any plane away from those.
+  T dv[kRPT][3], sc[kRPT][3];
+  auto coef = [&](int k, bool bulk) {
+    const int czt = bulk ? 2 : axis_count(k > 0, k < nz - 1, G.bc[4] == kDir, G.bc[5] == kDir);
+    const int cnw = bulk ? 2 : int(k > 0) + 1;
+    const T ww = (!bulk && k == 0) ? T(0.5) : T(1);
+    const bool pz = !bulk && k == pk, pz1 = !bulk && k - 1 == pk, kpos = bulk || k > 0;
+#pragma unroll
+    for (int r = 0; r < kRPT; ++r) {
+      const int i = i0 + tx, j = j0 + ty + r * kTYT;
+      const bool pc = i == pi && j == pj, pl = i - 1 == pi && j == pj, ps = i == pi && j - 1 == pj;
+      const int cx = axis_count(i > 0, i < nx - 1, G.bc[0] == kDir, G.bc[1] == kDir);
+      const int cy = axis_count(j > 0, j < ny - 1, G.bc[2] == kDir, G.bc[3] == kDir);
+      const T wu = i == 0 ? T(0.5) : T(1), wv = j == 0 ? T(0.5) : T(1);
+      dv[r][0] = T(int(i > 0) + 1) + wu * T(cy + czt);
+      dv[r][1] = T(int(j > 0) + 1) + wv * T(cx + czt);
+      dv[r][2] = T(cnw) + ww * T(cx + cy);
+      const int own = int(!(pz && pc));
+      const int ncell[3] = {own + int(i > 0 && !(pz && pl)), own + int(j > 0 && !(pz && ps)),
+                            own + int(kpos && !(pz1 && pc))};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T dt = (dv[r][c] + op.eta * T(ncell[c])) * op.ih2;
+        sc[r][c] = (MODE == kJacobi || MODE == kJacobiDot) ? omega * recip(dt) : recip(dt);
+      }
+    }
+  };
+  // Constant viscosity: each thread takes the divergence of its own cells
+  // from the face values it reads for its faces anyway; the 73 halo cells of
+  // the tile go to the threads t < 73: t <= 64 the row j0 - 1 (cell
+  // i0 - 1 + t), t = 65..72 the column i0 - 1 (row j0 - 1 + t - 64).
+  // (hcj, hci): that cell in the divergence array; hbits bit 0: it exists,
+  // bit 1: it lies in the pinned cell's column, bit 2 + r: the thread's own
+  // cell of row r lies in that column.
+  int hci = 0, hcj = 0;
+  unsigned hbits = 0;
+  if (!VARMU) {
+    const int t = threadIdx.x;
+    hci = t < kTX + 1 ? t : 0;
+    hcj = t < kTX + 1 ? 0 : t - kTX;
+    const int i = i0 - 1 + hci, j = j0 - 1 + hcj;
+    const bool ok = t < kTX + 1 + kTY && i >= 0 && i < nx && j >= 0 && j < ny;
+    hbits = (ok ? 1u : 0u) | (ok && i == pi && j == pj ? 2u : 0u);
+#pragma unroll
+    for (int r = 0; r < kRPT; ++r)
+      hbits |= (i0 + tx == pi && j0 + ty + r * kTYT == pj ? 4u : 0u) << r;
+    coef(0, true);
+  }
 
   T up[kRPT], vp[kRPT], wp[kRPT], cdp[kRPT];
   BRegs bA, bB;
@@ -272,8 +369,8 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
 
   const T eta = op.eta, ih2 = op.ih2;
   double part = 0.0;
-  // one z-plane: x of plane k+1 is in F and b of plane k in bc; F is
-  // refilled with plane k+3 and bc with b of plane k+2
+  // one z-plane (variable viscosity): x of plane k+1 is in F and b of plane
+  // k in bc; F is refilled with plane k+3 and bc with b of plane k+2
   auto step = [&](int k, FRegs& F, BRegs& bc) {
     const int s = (k - k0) & 1, s1 = s ^ 1;
     store_plane(s1, k + 1, F);
@@ -385,14 +482,14 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
               acc += eta * (cR - cdp[r]);
               d += eta * T(cnt);
             }
-            part += tile_finish<T, MODE>(fo[r][2], unsigned(k * pw) * E, k > 0 || unk_w0,
+            part += tile_finish<T, MODE>(fo[r][1], unsigned(k * pw) * E + dw, k > 0 || unk_w0,
                                          acc * ih2, d * ih2, xf, bc[r][2], ry, omega);
           }
         }
         // upper boundary faces are Dirichlet faces: keep them zero
         if (i == nx - 1) buf_store(T(0), ry, fo[r][0] + E, unsigned(k * pu) * E);
         if (j == ny - 1) buf_store(T(0), ry, fo[r][1] + unsigned(nx) * E, unsigned(k * pv) * E);
-        if (k == nz - 1) buf_store(T(0), ry, fo[r][2], unsigned(nz * pw) * E);
+        if (k == nz - 1) buf_store(T(0), ry, fo[r][1], unsigned(nz * pw) * E + dw);
         up[r] = S.u[s][jj][ii];
         vp[r] = S.v[s][jj][ii];
         wp[r] = S.w[s][jj][ii];
@@ -402,9 +499,92 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
     fetch_b(min(k + 2, k1 - 1), bc);
     __syncthreads();
   };
-  for (int k = k0; k < k1; k += 2) {
-    step(k, FA, bA);
-    if (k + 1 < k1) step(k + 1, FB, bB);
+
+  // Constant viscosity, one z-plane in two phases and two barriers: (A)
+  // read every face neighbour, form the viscous part of M x and the
+  // divergence of the own cells (written to LDS with the halo cells);
+  // (B) add the grad-div term from the divergences of the neighbour cells
+  // and finish.  The barrier before (A) of the next plane also orders the
+  // divergence reads of (B) before their next writes.
+  auto step_c = [&](int k, FRegs& F, BRegs& bc) {
+    const int s = (k - k0) & 1, s1 = s ^ 1;
+    store_plane(s1, k + 1, F);
+    __syncthreads();
+    fetch_plane(min(k + 3, k1), F);
+    const bool pz = k == pk;
+    const bool kbulk = k > 0 && k < nz - 1 && k != pk && k - 1 != pk;
+    if (!kbulk) coef(k, false);  // uniform branch
+    const T ww = k == 0 ? T(0.5) : T(1);
+    // across the barrier: au / av = viscous part of M x + eta x own-cell
+    // divergence for the u / v faces, and the face values (the next plane's
+    // z neighbours); the w-face has both adjacent cells in this column and is
+    // finished here
+    T au[kRPT], av[kRPT];
+#pragma unroll
+    for (int r = 0; r < kRPT; ++r) {
+      const int jj = ty + r * kTYT + 1, ii = tx + 1;
+      const int i = i0 + tx, j = j0 + ty + r * kTYT;
+      const T wu = i == 0 ? T(0.5) : T(1), wv = j == 0 ? T(0.5) : T(1);
+      const T uC = S.u[s][jj][ii], uR = S.u[s][jj][ii + 1], uT = S.u[s1][jj][ii];
+      const T vC = S.v[s][jj][ii], vN = S.v[s][jj + 1][ii], vT = S.v[s1][jj][ii];
+      const T wC = S.w[s][jj][ii], wT = S.w[s1][jj][ii];
+      const bool ok = i < nx && j < ny && !(pz && ((hbits >> (2 + r)) & 1u));
+      const T cR = ok ? (uC - uR) + (vC - vN) + (wC - wT) : T(0);
+      S.cd[jj][ii] = cR;
+      au[r] = dv[r][0] * uC + eta * cR -
+              ((S.u[s][jj][ii - 1] + uR) + wu * ((S.u[s][jj - 1][ii] + S.u[s][jj + 1][ii]) + (up[r] + uT)));
+      av[r] = dv[r][1] * vC + eta * cR -
+              ((S.v[s][jj - 1][ii] + vN) + wv * ((S.v[s][jj][ii - 1] + S.v[s][jj][ii + 1]) + (vp[r] + vT)));
+      const T aw = dv[r][2] * wC + eta * (cR - cdp[r]) -
+                   ((wp[r] + wT) + ww * ((S.w[s][jj][ii - 1] + S.w[s][jj][ii + 1]) +
+                                         (S.w[s][jj - 1][ii] + S.w[s][jj + 1][ii])));
+      if (i < nx && j < ny) {
+        part += tile_out<T, MODE>(fo[r][1], unsigned(k * pw) * E + dw, k > 0 || unk_w0, aw * ih2,
+                                  sc[r][2], wC, bc[r][2], ry);
+        if (k == nz - 1) buf_store(T(0), ry, fo[r][1], unsigned(nz * pw) * E + dw);
+      }
+      up[r] = uC;
+      vp[r] = vC;
+      wp[r] = wC;
+      cdp[r] = cR;
+    }
+    if (threadIdx.x < kTX + 1 + kTY) {
+      const int cj = hcj, ci = hci;
+      const bool ok = (hbits & 1u) && !(pz && (hbits & 2u));
+      const T v = (S.u[s][cj][ci] - S.u[s][cj][ci + 1]) + (S.v[s][cj][ci] - S.v[s][cj + 1][ci]) +
+                  (S.w[s][cj][ci] - S.w[s1][cj][ci]);
+      S.cd[cj][ci] = ok ? v : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRPT; ++r) {
+      const int jj = ty + r * kTYT + 1, ii = tx + 1;
+      const int i = i0 + tx, j = j0 + ty + r * kTYT;
+      if (i < nx && j < ny) {
+        part += tile_out<T, MODE>(fo[r][0], unsigned(k * pu) * E, i > 0 || unk_u0,
+                                  (au[r] - eta * S.cd[jj][ii - 1]) * ih2, sc[r][0], up[r],
+                                  bc[r][0], ry);
+        part += tile_out<T, MODE>(fo[r][1], unsigned(k * pv) * E, j > 0 || unk_v0,
+                                  (av[r] - eta * S.cd[jj - 1][ii]) * ih2, sc[r][1], vp[r],
+                                  bc[r][1], ry);
+        // upper boundary faces are Dirichlet faces: keep them zero
+        if (i == nx - 1) buf_store(T(0), ry, fo[r][0] + E, unsigned(k * pu) * E);
+        if (j == ny - 1) buf_store(T(0), ry, fo[r][1] + unsigned(nx) * E, unsigned(k * pv) * E);
+      }
+    }
+    if (!kbulk) coef(0, true);
+    fetch_b(min(k + 2, k1 - 1), bc);
+  };
+  if constexpr (VARMU) {
+    for (int k = k0; k < k1; k += 2) {
+      step(k, FA, bA);
+      if (k + 1 < k1) step(k + 1, FB, bB);
+    }
+  } else {
+    for (int k = k0; k < k1; k += 2) {
+      step_c(k, FA, bA);
+      if (k + 1 < k1) step_c(k + 1, FB, bB);
+    }
   }
   constexpr bool kRed = MODE == kApplyDot || MODE == kJacobiDot || MODE == kDinvM || MODE == kResidDot;
   if (kRed) {
