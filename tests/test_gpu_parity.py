@@ -239,15 +239,24 @@ def test_outputs_fully_written(name, grid, prec, smoother):
 @pytest.mark.parametrize("dim,n", [(2, 3), (3, 2)])
 def test_run_past_exhaustion_on_tiny_grids(dim, n):
     """Without a stopping tolerance (tol <= 0) on grids with a handful of
-    pressure unknowns, GKB runs three times as many steps as there are
-    unknowns, past the exhaustion of the Krylov space (where breakdown or
-    repeated converged values end or continue the recurrence): the same
-    status and K as the oracle, the same iterates, and the exact solution."""
+    pressure unknowns, GKB runs up to three times as many steps as there are
+    unknowns, past the exhaustion of the Krylov space, and ends with the
+    exact solution, equal to the oracle's.  Past exhaustion beta carries
+    only the inner solves' error, which is of the size of the breakdown
+    threshold (beta <= 1e-13 alpha at inner tolerance 1e-13: the oracle
+    itself stops at step 5 on the 3D grid with inner tolerance 1e-13 and
+    runs all 21 steps with 1e-14), so whether a step is flagged as a
+    breakdown is decided by rounding: either status is valid, and K must
+    agree when the two statuses do."""
     _say("past exhaustion", dim, n)
     pr = P.stokes_problem(dim, n, seed=4, eta=10.0)
     n_unknown = pr.grid.n_cells - 1
     w, p, info, ref = _gkb_pair(pr, 0.0, 3 * n_unknown)
-    assert info["status"] == ref["status"] and info["iterations"] == ref["K"]
+    assert info["status"] in (0, 1) and ref["status"] in (0, 1)
+    if info["status"] == ref["status"]:
+        assert info["iterations"] == ref["K"]
+    for st, k in ((info["status"], info["iterations"]), (ref["status"], ref["K"])):
+        assert (k == 3 * n_unknown) if st == 1 else (k < 3 * n_unknown)
     assert _rel(w, ref["w"]) <= 1e-10 and _rel(p, ref["p"]) <= 1e-10
     _, _, nr = oracle.saddle_residual(pr.grid, pr.g, pr.r, w, p)
     assert nr[0] <= 1e-10 * nr[3]
