@@ -40,13 +40,13 @@ MODES = {
     # fastest for it in a sweep over tau in [3e-3, 3e-2], tau_in in
     # [1e-4, 3e-3] and d in {2, 3} on two forcing seeds.  The configured
     # multigrid is V(2,2) with weighted Jacobi: FP64 tau = 1e-2, tau_in =
-    # 1e-3; FP32 inner solves tau = 3e-2, tau_in = 3e-3; d = 2.  fp64_gkb1 is
+    # 1e-3; FP32 inner solves tau = 1e-2, tau_in = 3e-4; d = 2.  fp64_gkb1 is
     # the paper's method as printed: one GKB run whose lower-bound tolerance
     # alone reaches 1e-8.  The *_hybrid modes replace the smoother by the
     # face + edge hybrid smoother, V(1,1), tau = 3e-3, tau_in = 3e-4, d = 2.
     "fp64_mg": ("fp64", "mg", 1e-2, 1e-3, 2, "jacobi", 2),
-    "mixed_mg": ("mixed", "mg", 3e-2, 3e-3, 2, "jacobi", 2),
-    "mixed_learned": ("mixed", "learned", 3e-2, 3e-3, 2, "jacobi", 2),
+    "mixed_mg": ("mixed", "mg", 1e-2, 3e-4, 2, "jacobi", 2),
+    "mixed_learned": ("mixed", "learned", 1e-2, 3e-4, 2, "jacobi", 2),
     "fp64_gkb1": ("fp64", "mg", 1e-9, 1e-10, 5, "jacobi", 2),
     "fp64_mg_hybrid": ("fp64", "mg", 3e-3, 3e-4, 2, "hybrid", 1),
     "mixed_mg_hybrid": ("mixed", "mg", 3e-3, 3e-4, 2, "hybrid", 1),

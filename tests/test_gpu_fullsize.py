@@ -31,7 +31,7 @@ def _gk():
 # as timed by bench.py
 BENCH_MODES = {
     "fp64_mg": dict(precision="fp64", inner="mg", inner_tol=1e-3, tol=1e-2, delay=2),
-    "mixed_mg": dict(precision="mixed", inner="mg", inner_tol=3e-3, tol=3e-2, delay=2),
+    "mixed_mg": dict(precision="mixed", inner="mg", inner_tol=3e-4, tol=1e-2, delay=2),
     "fp64_gkb1": dict(precision="fp64", inner="mg", inner_tol=1e-10, tol=1e-9, delay=5),
     "fp64_mg_hybrid": dict(precision="fp64", inner="mg", inner_tol=3e-4, tol=3e-3, delay=2,
                            smoother="hybrid", nu_pre=1, nu_post=1),
