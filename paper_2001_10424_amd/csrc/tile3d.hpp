@@ -1,9 +1,9 @@
 // LDS-tiled 3D MAC stencil for M = W + eta A A^T (and the Jacobi / residual
 // variants built on it) on grids whose +x, +y, +z sides are DIRICHLET.
 //
-// A block of 256 threads (4 wave64) owns a tile of 64 x 8 cells in x-y and
+// A block of 256 threads (4 wave64) owns a tile of 64 x 4 cells in x-y and
 // marches through `tz` consecutive z-planes.  Each thread owns one x
-// position and two y rows and produces the three "lower" faces u(i,j,k),
+// position and kRPT y rows and produces the three "lower" faces u(i,j,k),
 // v(i,j,k), w(i,j,k) of its cells; the upper boundary faces (i = nx, ...)
 // are Dirichlet faces and are written as 0 by the last row / column / plane.
 //
@@ -22,7 +22,11 @@ namespace gkb {
 
 constexpr int kTX = 64;          // tile width (cells) = threads in x
 constexpr int kTYT = 256 / kTX;  // threads in y
-constexpr int kRPT = 2;          // rows per thread
+// rows per thread: one row (64 x 4 tiles, 8 planes per block at 128^3)
+// measured 4% faster in FP32 and 5% in FP64 than two rows (64 x 8 tiles,
+// 4 planes per block): half the per-thread state, the per-block set-up
+// spread over twice the planes
+constexpr int kRPT = 1;
 constexpr int kTY = kTYT * kRPT; // tile height (cells)
 constexpr int kLX = kTX + 2;
 constexpr int kLY = kTY + 2;
@@ -164,9 +168,8 @@ __device__ __forceinline__ int axis_count(bool lo_in, bool hi_in, bool lo_wall, 
 // one never waits for the loads into the other; the prologue issues its four
 // planes at once.
 // FP32: at least 4 waves per SIMD (4 blocks per CU, all of the 128^3 grid
-// in one round) fit in 128 VGPRs without spills (measured 17% faster than
-// leaving the register count free); FP64 spills under any cap and runs
-// fastest without one
+// in one round; the one-row kernels need about 85 VGPRs, so the cap does not
+// bind, and 6 waves per SIMD measured no faster); FP64 runs uncapped
 template <typename T>
 constexpr int kTileMinWaves = sizeof(T) == 4 ? 4 : 1;
 
