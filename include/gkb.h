@@ -225,8 +225,10 @@ int gkb_residual(gkb_ctx *c, const double *g, const double *r, const double *w,
 
 /* Launch one finest-grid kernel of the inner solver `reps` times back to
    back on the context's stream (working precision of the inner solve, on
-   the context's own PCG buffers) and return the average duration per launch
-   in milliseconds, measured with HIP events recorded on that stream.  Needs
+   the context's own PCG buffers; the launches are captured into one HIP
+   graph and replayed, as the solver replays its PCG iterations) and return
+   the average time per launch in milliseconds, measured with HIP events
+   recorded on that stream around the replay.  Needs
    inner = GKB_INNER_MG or GKB_INNER_LEARNED.  Does not change solver state
    other than scratch vectors. */
 int gkb_time_kernel(gkb_ctx *c, int kernel, int reps, double *avg_ms);

@@ -1367,14 +1367,27 @@ int time_kernel_impl(gkb_ctx* c, Inner<T>& in, int kernel, int reps, double* avg
     else
       face_op<T, kResid>(c, L.op, L.fl, in.z, in.r, L.rb, T(0), nullptr, nullptr);
   };
+  // the launches are captured into one HIP graph and replayed, as the solver
+  // replays its PCG iterations, so the per-launch time is the kernel's
+  // duration plus the graph's (small) gap between nodes
   one();  // warm-up launch
-  HIPCK(hipEventRecord(e0, c->cs));
+  hipGraph_t gr;
+  hipGraphExec_t ge = nullptr;
+  HIPCK(hipStreamBeginCapture(c->cs, hipStreamCaptureModeThreadLocal));
   for (int i = 0; i < reps; ++i) one();
+  HIPCK(hipStreamEndCapture(c->cs, &gr));
+  const hipError_t ie = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(gr);
+  HIPCK(ie);
+  HIPCK(hipGraphLaunch(ge, c->cs));  // warm-up replay
+  HIPCK(hipEventRecord(e0, c->cs));
+  HIPCK(hipGraphLaunch(ge, c->cs));
   HIPCK(hipEventRecord(e1, c->cs));
   HIPCK(hipEventSynchronize(e1));
   float ms = 0.f;
   HIPCK(hipEventElapsedTime(&ms, e0, e1));
   *avg_ms = double(ms) / reps;
+  (void)hipGraphExecDestroy(ge);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return GKB_OK;

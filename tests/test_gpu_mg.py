@@ -227,3 +227,26 @@ def test_refinement_stops_when_a_sweep_does_not_reduce_the_residual():
     assert nr[0] <= nr[3]
     assert abs(info["residual"] - nr[0] / nr[3]) <= 1e-6 * nr[0] / nr[3]
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_time_kernel_replays_and_leaves_the_solver_usable(prec):
+    """gkb_time_kernel (graph replay of the finest-grid sweep, apply and
+    residual kernels) returns a positive time per launch, can be called
+    repeatedly, and the next solve gives bitwise the same result as before."""
+    _say("time kernel", prec)
+    torch = __import__("torch")
+    gk = _gk()
+    pr = P.stokes_problem(3, 32, seed=2, eta=1e2)
+    s = gk.Solver(pr.grid, None, pr.eta, inner="mg", precision=prec, inner_tol=1e-6,
+                  refine_tol=1e-8, max_sweeps=10)
+    g, r = _dev(pr.g), _dev(pr.r)
+    w0, p0, _ = s.solve(g, r, tol=1e-3, delay=2)
+    w0, p0 = w0.clone(), p0.clone()
+    for k in ("smooth", "apply", "resid", "smooth"):
+        ms = s.time_kernel(k, 10)
+        assert 0.0 < ms < 50.0, (k, ms)
+    w1, p1, _ = s.solve(g, r, tol=1e-3, delay=2)
+    torch.cuda.synchronize()
+    assert torch.equal(w0, w1) and torch.equal(p0, p1)
+    s.close()
