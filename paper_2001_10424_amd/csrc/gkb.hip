@@ -234,23 +234,31 @@ void face_op(gkb_ctx* c, const Op<T>& op, const FaceLaunch& fl, const T* x, cons
   const bool vm = op.mu != nullptr;
   const int kz = fl.kz, zc = fl.zchunks;
   hipStream_t s = c->cs;
-  if (fl.tiled && MODE != kJacobi0 && MODE != kDiag) {
+  if constexpr (MODE == kJacobiZ) {
+    // tiled grids with constant viscosity only (the caller checks)
     const bool fine = op.g.m_full == c->g.m_full;
-    if (vm) {
-      if (fine) k_tile3d<T, true, MODE, true><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st);
-      else k_tile3d<T, true, MODE, false><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st);
-    } else {
-      if (fine) k_tile3d<T, false, MODE, true><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st);
-      else k_tile3d<T, false, MODE, false><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st);
-    }
+    if (fine) k_tile3d<T, false, MODE, true><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st);
+    else k_tile3d<T, false, MODE, false><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st);
     return;
-  }
-  if (op.g.dim == 2) {
-    if (vm) k_face_op<T, 2, true, MODE><<<fl.grid, kBlock, 0, s>>>(op, x, b, y, omega, kz, zc, partial, st);
-    else k_face_op<T, 2, false, MODE><<<fl.grid, kBlock, 0, s>>>(op, x, b, y, omega, kz, zc, partial, st);
   } else {
-    if (vm) k_face_op<T, 3, true, MODE><<<fl.grid, kBlock, 0, s>>>(op, x, b, y, omega, kz, zc, partial, st);
-    else k_face_op<T, 3, false, MODE><<<fl.grid, kBlock, 0, s>>>(op, x, b, y, omega, kz, zc, partial, st);
+    if (fl.tiled && MODE != kJacobi0 && MODE != kDiag) {
+      const bool fine = op.g.m_full == c->g.m_full;
+      if (vm) {
+        if (fine) k_tile3d<T, true, MODE, true><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st);
+        else k_tile3d<T, true, MODE, false><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st);
+      } else {
+        if (fine) k_tile3d<T, false, MODE, true><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st);
+        else k_tile3d<T, false, MODE, false><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st);
+      }
+      return;
+    }
+    if (op.g.dim == 2) {
+      if (vm) k_face_op<T, 2, true, MODE><<<fl.grid, kBlock, 0, s>>>(op, x, b, y, omega, kz, zc, partial, st);
+      else k_face_op<T, 2, false, MODE><<<fl.grid, kBlock, 0, s>>>(op, x, b, y, omega, kz, zc, partial, st);
+    } else {
+      if (vm) k_face_op<T, 3, true, MODE><<<fl.grid, kBlock, 0, s>>>(op, x, b, y, omega, kz, zc, partial, st);
+      else k_face_op<T, 3, false, MODE><<<fl.grid, kBlock, 0, s>>>(op, x, b, y, omega, kz, zc, partial, st);
+    }
   }
 }
 
@@ -314,12 +322,23 @@ void vcycle(gkb_ctx* c, Inner<T>& in, int l, const T* b, T* x, double* dot_parti
   const T* cur = nullptr;
   int k = 0;
   if (n1 > 0) {
+    int i = 1;
     ++k;
-    T* o = dst(k);
-    if (!first_done) face_op<T, kJacobi0>(c, L.op, L.fl, nullptr, b, o, om, nullptr, st);
-    if (hybrid) edge_step<T>(c, L, b, o, st);
-    cur = o;
-    for (int i = 1; i < n1; ++i) {
+    // the first two sweeps from a zero guess in one pass (tiled grids,
+    // constant viscosity, weighted-Jacobi smoother)
+    const bool two = !first_done && n1 >= 2 && !hybrid && L.fl.tiled && L.op.mu == nullptr;
+    if (two) {
+      ++k;
+      ++i;
+      face_op<T, kJacobiZ>(c, L.op, L.fl, b, b, dst(k), om, nullptr, st);
+      cur = dst(k);
+    } else {
+      T* o = dst(k);
+      if (!first_done) face_op<T, kJacobi0>(c, L.op, L.fl, nullptr, b, o, om, nullptr, st);
+      if (hybrid) edge_step<T>(c, L, b, o, st);
+      cur = o;
+    }
+    for (; i < n1; ++i) {
       ++k;
       T* o2 = dst(k);
       face_op<T, kJacobi>(c, L.op, L.fl, cur, b, o2, om, nullptr, st);

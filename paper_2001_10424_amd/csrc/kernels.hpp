@@ -83,7 +83,10 @@ enum MMode {
   kDinvM = 5,      // y = (M x) / D, partial y.y
   kJacobi0 = 6,    // y = omega b / D   (first sweep from a zero guess)
   kDiag = 7,       // y = D
-  kResidDot = 8    // y = b - M x, partial y.y
+  kResidDot = 8,   // y = b - M x, partial y.y
+  kJacobiZ = 9     // two sweeps from a zero guess: y = x1 + omega (b - M x1) / D
+                   // with x1 = omega b / D (x1 formed while staging; tiled
+                   // kernel, constant viscosity only; x = b)
 };
 
 // Thread mapping: blockIdx.z = component * zchunks + z-chunk; each block

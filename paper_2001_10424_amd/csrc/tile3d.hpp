@@ -96,7 +96,8 @@ __device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, un
 
 template <int MODE>
 constexpr bool reads_b() {
-  return MODE == kJacobi || MODE == kJacobiDot || MODE == kResid || MODE == kResidDot;
+  return MODE == kJacobi || MODE == kJacobiDot || MODE == kResid || MODE == kResidDot ||
+         MODE == kJacobiZ;
 }
 
 // bf: b at the face (prefetched by the caller when the mode reads b); unk:
@@ -110,7 +111,7 @@ __device__ __forceinline__ double tile_finish(unsigned voff, unsigned soff, bool
   if (MODE == kApply || MODE == kApplyDot) {
     out = unk ? mx : T(0);
     if (MODE == kApplyDot) part = double(xf) * double(out);
-  } else if (MODE == kJacobi || MODE == kJacobiDot) {
+  } else if (MODE == kJacobi || MODE == kJacobiDot || MODE == kJacobiZ) {
     out = unk ? xf + omega * (bf - mx) * recip(d) : T(0);
     if (MODE == kJacobiDot) part = double(bf) * double(out);
   } else if (MODE == kResid || MODE == kResidDot) {
@@ -135,7 +136,7 @@ __device__ __forceinline__ double tile_out(unsigned voff, unsigned soff, bool un
   if (MODE == kApply || MODE == kApplyDot) {
     out = unk ? mx : T(0);
     if (MODE == kApplyDot) part = double(xf) * double(out);
-  } else if (MODE == kJacobi || MODE == kJacobiDot) {
+  } else if (MODE == kJacobi || MODE == kJacobiDot || MODE == kJacobiZ) {
     out = unk ? xf + (bf - mx) * sc : T(0);
     if (MODE == kJacobiDot) part = double(bf) * double(out);
   } else if (MODE == kResid || MODE == kResidDot) {
@@ -235,18 +236,67 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
       F[2][q] = buf_load<T>(rx, hv[q], unsigned(kk * pw) * E + dw);
     }
   };
+  // pinned cell (pk = -2: none)
+  const int nxy = nx * ny;
+  const int pk = G.pin >= 0 ? G.pin / nxy : -2;
+  const int pj = G.pin >= 0 ? (G.pin - pk * nxy) / nx : -3;
+  const int pi = G.pin >= 0 ? G.pin - pk * nxy - pj * nx : -3;
+
+  // kJacobiZ (x = b): the staged values are the first sweep from a zero
+  // guess, x1 = omega b / D.  zs holds omega / D of the staged elements for
+  // every plane whose diagonal is the bulk one (not the first or last plane,
+  // not next to the pinned cell), taken on plane zb (-1: no such plane, the
+  // scales are computed per plane); other planes compute them (uniform
+  // branch, at most four planes of a grid)
+  constexpr bool kZ = MODE == kJacobiZ;
+  static_assert(!(kZ && VARMU), "the two-sweep mode is for constant viscosity");
+  auto zbulk = [&](int k) { return k > 0 && k < nz - 1 && k != pk && k - 1 != pk; };
+  auto zscale = [&](int q, int c, int k) -> T {
+    const int e = threadIdx.x + q * 256;
+    const int jj = e / kLX, ii = e - jj * kLX;
+    const int i = i0 - 1 + ii, j = j0 - 1 + jj;
+    if (!((hmask >> (3 * q + c)) & 1u)) return T(0);  // not staged: any value
+    const T d = c == 0   ? diag_M<T, 3, false, 0>(op, i, j, k)
+                : c == 1 ? diag_M<T, 3, false, 1>(op, i, j, k)
+                         : diag_M<T, 3, false, 2>(op, i, j, k);
+    return omega * recip(d);
+  };
+  int zb = -1;
+  T zs[3][kPer];
+  if (kZ) {
+    for (int kk = 1; kk < min(nz - 1, 4) && zb < 0; ++kk)
+      if (zbulk(kk)) zb = kk;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) zs[c][q] = zb >= 0 ? zscale(q, c, zb) : T(0);
+  }
   auto store_plane = [&](int s, int k, const FRegs& F) {
     const bool kin = k >= 0 && k < nz;
     const bool kw = kin && (k > 0 || unk_w0);
+    T z[3][kPer];
+    if (kZ) {
+      if (zb >= 0 && zbulk(k)) {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) z[c][q] = zs[c][q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) z[c][q] = kin ? zscale(q, c, k) : T(0);
+      }
+    }
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const int e = threadIdx.x + q * 256;
       if (e < kLX * kLY) {
         const int jj = e / kLX, ii = e - jj * kLX;
         const unsigned m = hmask >> (3 * q);
-        S.u[s][jj][ii] = (kin && (m & 1u)) ? F[0][q] : T(0);
-        S.v[s][jj][ii] = (kin && (m & 2u)) ? F[1][q] : T(0);
-        S.w[s][jj][ii] = (kw && (m & 4u)) ? F[2][q] : T(0);
+        S.u[s][jj][ii] = (kin && (m & 1u)) ? (kZ ? F[0][q] * z[0][q] : F[0][q]) : T(0);
+        S.v[s][jj][ii] = (kin && (m & 2u)) ? (kZ ? F[1][q] * z[1][q] : F[1][q]) : T(0);
+        S.w[s][jj][ii] = (kw && (m & 4u)) ? (kZ ? F[2][q] * z[2][q] : F[2][q]) : T(0);
       }
     }
   };
@@ -276,11 +326,6 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
     }
   };
 
-  // pinned cell (pk = -2: none)
-  const int nxy = nx * ny;
-  const int pk = G.pin >= 0 ? G.pin / nxy : -2;
-  const int pj = G.pin >= 0 ? (G.pin - pk * nxy) / nx : -3;
-  const int pi = G.pin >= 0 ? G.pin - pk * nxy - pj * nx : -3;
 
   // Constant viscosity: the neighbours outside the array and the
   // non-unknown faces are zeros in LDS and in the z registers, so the
@@ -311,7 +356,8 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const T dt = (dv[r][c] + op.eta * T(ncell[c])) * op.ih2;
-        sc[r][c] = (MODE == kJacobi || MODE == kJacobiDot) ? omega * recip(dt) : recip(dt);
+        sc[r][c] = (MODE == kJacobi || MODE == kJacobiDot || MODE == kJacobiZ) ? omega * recip(dt)
+                                                                               : recip(dt);
       }
     }
   };

@@ -67,6 +67,9 @@ def test_vcycle_symmetric_positive(name, grid, eta, varmu, smoother):
 
 TILED_CASES = MG_CASES[:2] + [
     ("3d_lower_natural", P.Grid(3, (16, 24, 16), 1 / 16, (N, D, D, D, D, D), -1), 10.0, True),
+    ("3d_lower_natural_const", P.Grid(3, (16, 24, 16), 1 / 16, (N, D, N, D, D, D), -1), 10.0,
+     False),
+    ("3d_pin_mid", P.Grid(3, (16, 8, 12), 1 / 8, (D,) * 6, 5 * 16 * 8 + 3 * 16 + 7), 1e2, False),
 ]
 
 
