@@ -228,30 +228,34 @@ namespace {
 
 // ------------------------------------------------------------ launches
 
+// ec / Gc: coarse correction and coarse grid of kJacobiP (unused otherwise)
 template <typename T, int MODE>
 void face_op(gkb_ctx* c, const Op<T>& op, const FaceLaunch& fl, const T* x, const T* b, T* y,
-             T omega, double* partial, const PcgState* st) {
+             T omega, double* partial, const PcgState* st, const T* ec = nullptr,
+             const Grid* Gc = nullptr) {
   const bool vm = op.mu != nullptr;
   const int kz = fl.kz, zc = fl.zchunks;
   hipStream_t s = c->cs;
+  const Grid gc = Gc ? *Gc : op.g;
   if constexpr (MODE == kJacobiZ) {
     // tiled grids with constant viscosity only (the caller checks)
     const bool fine = op.g.m_full == c->g.m_full;
-    if (fine) k_tile3d<T, false, MODE, true><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st);
-    else k_tile3d<T, false, MODE, false><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st);
+    if (fine) k_tile3d<T, false, MODE, true><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st, ec, gc);
+    else k_tile3d<T, false, MODE, false><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st, ec, gc);
     return;
   } else {
     if (fl.tiled && MODE != kJacobi0 && MODE != kDiag) {
       const bool fine = op.g.m_full == c->g.m_full;
       if (vm) {
-        if (fine) k_tile3d<T, true, MODE, true><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st);
-        else k_tile3d<T, true, MODE, false><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st);
+        if (fine) k_tile3d<T, true, MODE, true><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st, ec, gc);
+        else k_tile3d<T, true, MODE, false><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st, ec, gc);
       } else {
-        if (fine) k_tile3d<T, false, MODE, true><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st);
-        else k_tile3d<T, false, MODE, false><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st);
+        if (fine) k_tile3d<T, false, MODE, true><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st, ec, gc);
+        else k_tile3d<T, false, MODE, false><<<fl.tgrid, 256, 0, s>>>(op, x, b, y, omega, fl.tz, partial, st, ec, gc);
       }
       return;
     }
+    if constexpr (MODE == kJacobiP) return;  // tiled grids only (the caller checks)
     if (op.g.dim == 2) {
       if (vm) k_face_op<T, 2, true, MODE><<<fl.grid, kBlock, 0, s>>>(op, x, b, y, omega, kz, zc, partial, st);
       else k_face_op<T, 2, false, MODE><<<fl.grid, kBlock, 0, s>>>(op, x, b, y, omega, kz, zc, partial, st);
@@ -365,11 +369,24 @@ void vcycle(gkb_ctx* c, Inner<T>& in, int l, const T* b, T* x, double* dot_parti
     it = (n2 % 2 == 0) ? x : L.t;
     k_fill<T><<<vec_blocks(L.g.m_full), kBlock, 0, s>>>(L.g.m_full, T(0), it);
   }
-  const dim3 fg = transfer_grid(L.g);
-  if (L.g.dim == 2) k_prolong_add<T, 2><<<fg, kBlock, 0, s>>>(L.g, Lc.g, Lc.x, it, st);
-  else k_prolong_add<T, 3><<<fg, kBlock, 0, s>>>(L.g, Lc.g, Lc.x, it, st);
-  cur = it;
-  for (int i = 0; i < n2; ++i) {
+  // the coarse-grid correction is added while the first post-smoothing sweep
+  // stages its input (tiled grids, weighted-Jacobi smoother, that sweep not
+  // the one that forms the dot product)
+  const bool pro = cur && n2 >= 1 && !hybrid && L.fl.tiled && !(n2 == 1 && dot_partial);
+  int i0 = 0;
+  if (pro) {
+    ++k;
+    T* o = (it == x) ? L.t : x;
+    face_op<T, kJacobiP>(c, L.op, L.fl, it, b, o, om, nullptr, st, Lc.x, &Lc.g);
+    cur = o;
+    i0 = 1;
+  } else {
+    const dim3 fg = transfer_grid(L.g);
+    if (L.g.dim == 2) k_prolong_add<T, 2><<<fg, kBlock, 0, s>>>(L.g, Lc.g, Lc.x, it, st);
+    else k_prolong_add<T, 3><<<fg, kBlock, 0, s>>>(L.g, Lc.g, Lc.x, it, st);
+    cur = it;
+  }
+  for (int i = i0; i < n2; ++i) {
     ++k;
     T* o = (cur == x) ? L.t : x;
     const bool last = (i == n2 - 1);

@@ -84,9 +84,12 @@ enum MMode {
   kJacobi0 = 6,    // y = omega b / D   (first sweep from a zero guess)
   kDiag = 7,       // y = D
   kResidDot = 8,   // y = b - M x, partial y.y
-  kJacobiZ = 9     // two sweeps from a zero guess: y = x1 + omega (b - M x1) / D
+  kJacobiZ = 9,    // two sweeps from a zero guess: y = x1 + omega (b - M x1) / D
                    // with x1 = omega b / D (x1 formed while staging; tiled
                    // kernel, constant viscosity only; x = b)
+  kJacobiP = 10    // sweep after the coarse-grid correction: y = x' + omega
+                   // (b - M x') / D with x' = x + P e (prolongation of the
+                   // coarse correction e added while staging; tiled kernel)
 };
 
 // Thread mapping: blockIdx.z = component * zchunks + z-chunk; each block

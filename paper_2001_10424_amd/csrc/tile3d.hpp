@@ -97,7 +97,7 @@ __device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, un
 template <int MODE>
 constexpr bool reads_b() {
   return MODE == kJacobi || MODE == kJacobiDot || MODE == kResid || MODE == kResidDot ||
-         MODE == kJacobiZ;
+         MODE == kJacobiZ || MODE == kJacobiP;
 }
 
 // bf: b at the face (prefetched by the caller when the mode reads b); unk:
@@ -111,7 +111,7 @@ __device__ __forceinline__ double tile_finish(unsigned voff, unsigned soff, bool
   if (MODE == kApply || MODE == kApplyDot) {
     out = unk ? mx : T(0);
     if (MODE == kApplyDot) part = double(xf) * double(out);
-  } else if (MODE == kJacobi || MODE == kJacobiDot || MODE == kJacobiZ) {
+  } else if (MODE == kJacobi || MODE == kJacobiDot || MODE == kJacobiZ || MODE == kJacobiP) {
     out = unk ? xf + omega * (bf - mx) * recip(d) : T(0);
     if (MODE == kJacobiDot) part = double(bf) * double(out);
   } else if (MODE == kResid || MODE == kResidDot) {
@@ -136,7 +136,7 @@ __device__ __forceinline__ double tile_out(unsigned voff, unsigned soff, bool un
   if (MODE == kApply || MODE == kApplyDot) {
     out = unk ? mx : T(0);
     if (MODE == kApplyDot) part = double(xf) * double(out);
-  } else if (MODE == kJacobi || MODE == kJacobiDot || MODE == kJacobiZ) {
+  } else if (MODE == kJacobi || MODE == kJacobiDot || MODE == kJacobiZ || MODE == kJacobiP) {
     out = unk ? xf + (bf - mx) * sc : T(0);
     if (MODE == kJacobiDot) part = double(bf) * double(out);
   } else if (MODE == kResid || MODE == kResidDot) {
@@ -178,7 +178,8 @@ template <typename T, bool VARMU, int MODE, bool FINE>
 __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, const T* __restrict__ x,
                                                 const T* __restrict__ b, T* __restrict__ y,
                                                 T omega, int tz, double* __restrict__ partial,
-                                                const PcgState* __restrict__ st) {
+                                                const PcgState* __restrict__ st,
+                                                const T* __restrict__ ec, Grid Gc) {
   if (st && st->done) return;
   __shared__ TileLds<T> S;
   const Grid& G = op.g;
@@ -226,14 +227,67 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
     hmask |= (ov ? 2u : 0u) << (3 * q);
     hmask |= (in ? 4u : 0u) << (3 * q);
   }
-  typedef T FRegs[3][kPer];
+  // kJacobiP: the staged values are x + P e, the prolongation of the coarse
+  // correction e on the grid Gc (a fine face on a coarse face takes its
+  // value, a face between two coarse faces their mean; constant across the
+  // two fine cells in the tangential directions; non-unknown coarse faces
+  // count as 0).  Per staged element: in-plane index of the coarse u and v
+  // faces at (i/2, j/2) (w shares v's: both arrays are nx/2 wide) and six
+  // bits: odd i, odd j, coarse u faces I and I+1 unknown, coarse v faces J
+  // and J+1 unknown.  The coarse values (faces I / I+1, J / J+1, coarse
+  // planes K / K+1) are prefetched with the plane.
+  constexpr bool kP = MODE == kJacobiP;
+  constexpr int kPC = kP ? 6 : 1;
+  unsigned pcu[kPer], pcv[kPer], pbits = 0;
+  const __amdgpu_buffer_rsrc_t rc = kP ? buf_rsrc(ec, unsigned(Gc.m_full) * E) : rx;
+  const unsigned dwc = kP ? unsigned(Gc.off[2] - Gc.off[1]) * E : 0u;
+  if (kP) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = threadIdx.x + q * 256;
+      const int jj = e / kLX, ii = e - jj * kLX;
+      const int i = i0 - 1 + ii, j = j0 - 1 + jj;
+      const bool in = (hmask >> (3 * q + 2)) & 1u;
+      const int I = in ? i >> 1 : 0, J = in ? j >> 1 : 0;
+      pcu[q] = unsigned(Gc.off[0] + J * Gc.ext[0][0] + I) * E;
+      pcv[q] = unsigned(Gc.off[1] + J * Gc.ext[1][0] + I) * E;
+      const bool uI = !((I == 0 && Gc.bc[0] == kDir) || (I == Gc.n[0] && Gc.bc[1] == kDir));
+      const bool uI1 = !(I + 1 == Gc.n[0] && Gc.bc[1] == kDir);
+      const bool vJ = !((J == 0 && Gc.bc[2] == kDir) || (J == Gc.n[1] && Gc.bc[3] == kDir));
+      const bool vJ1 = !(J + 1 == Gc.n[1] && Gc.bc[3] == kDir);
+      const unsigned bits = (i & 1 ? 1u : 0u) | (j & 1 ? 2u : 0u) | (uI ? 4u : 0u) |
+                            (uI1 ? 8u : 0u) | (vJ ? 16u : 0u) | (vJ1 ? 32u : 0u);
+      pbits |= bits << (6 * q);
+    }
+  }
+  struct FRegs {
+    T v[3][kPer];
+    T c[kPC][kPer];  // kJacobiP: coarse u(I), u(I+1), v(J), v(J+1), w(K), w(K+1)
+  };
   auto fetch_plane = [&](int k, FRegs& F) {
     const int kk = min(max(k, 0), nz - 1);
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-      F[0][q] = buf_load<T>(rx, hu[q], unsigned(kk * pu) * E);
-      F[1][q] = buf_load<T>(rx, hv[q], unsigned(kk * pv) * E);
-      F[2][q] = buf_load<T>(rx, hv[q], unsigned(kk * pw) * E + dw);
+      F.v[0][q] = buf_load<T>(rx, hu[q], unsigned(kk * pu) * E);
+      F.v[1][q] = buf_load<T>(rx, hv[q], unsigned(kk * pv) * E);
+      F.v[2][q] = buf_load<T>(rx, hv[q], unsigned(kk * pw) * E + dw);
+    }
+    if (kP) {
+      const int K = kk >> 1, K1 = min(K + 1, Gc.ext[2][2] - 1);
+      const unsigned su = unsigned(K * Gc.ext[0][0] * Gc.ext[0][1]) * E;
+      const unsigned sv = unsigned(K * Gc.ext[1][0] * Gc.ext[1][1]) * E;
+      const unsigned sw = unsigned(K * Gc.ext[2][0] * Gc.ext[2][1]) * E + dwc;
+      const unsigned sw1 = unsigned(K1 * Gc.ext[2][0] * Gc.ext[2][1]) * E + dwc;
+      const unsigned rowv = unsigned(Gc.ext[1][0]) * E;
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        F.c[0][q] = buf_load<T>(rc, pcu[q], su);
+        F.c[1][q] = buf_load<T>(rc, pcu[q] + E, su);
+        F.c[2][q] = buf_load<T>(rc, pcv[q], sv);
+        F.c[3][q] = buf_load<T>(rc, pcv[q] + rowv, sv);
+        F.c[4][q] = buf_load<T>(rc, pcv[q], sw);
+        F.c[5][q] = buf_load<T>(rc, pcv[q], sw1);
+      }
     }
   };
   // pinned cell (pk = -2: none)
@@ -274,6 +328,28 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
   auto store_plane = [&](int s, int k, const FRegs& F) {
     const bool kin = k >= 0 && k < nz;
     const bool kw = kin && (k > 0 || unk_w0);
+    T val[3][kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) val[c][q] = F.v[c][q];
+    if (kP && kin) {
+      // coarse plane K = k / 2; a w face on an odd plane lies between K and K+1
+      const int K = k >> 1;
+      const bool wK = !((K == 0 && Gc.bc[4] == kDir) || (K == Gc.n[2] && Gc.bc[5] == kDir));
+      const bool wK1 = !(K + 1 == Gc.n[2] && Gc.bc[5] == kDir);
+      const bool oddk = k & 1;
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const unsigned bq = pbits >> (6 * q);
+        const T u0 = (bq & 4u) ? F.c[0][q] : T(0), u1 = (bq & 8u) ? F.c[1][q] : T(0);
+        const T v0 = (bq & 16u) ? F.c[2][q] : T(0), v1 = (bq & 32u) ? F.c[3][q] : T(0);
+        const T w0 = wK ? F.c[4][q] : T(0), w1 = wK1 ? F.c[5][q] : T(0);
+        val[0][q] += (bq & 1u) ? T(0.5) * (u0 + u1) : u0;
+        val[1][q] += (bq & 2u) ? T(0.5) * (v0 + v1) : v0;
+        val[2][q] += oddk ? T(0.5) * (w0 + w1) : w0;
+      }
+    }
     T z[3][kPer];
     if (kZ) {
       if (zb >= 0 && zbulk(k)) {
@@ -294,9 +370,9 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
       if (e < kLX * kLY) {
         const int jj = e / kLX, ii = e - jj * kLX;
         const unsigned m = hmask >> (3 * q);
-        S.u[s][jj][ii] = (kin && (m & 1u)) ? (kZ ? F[0][q] * z[0][q] : F[0][q]) : T(0);
-        S.v[s][jj][ii] = (kin && (m & 2u)) ? (kZ ? F[1][q] * z[1][q] : F[1][q]) : T(0);
-        S.w[s][jj][ii] = (kw && (m & 4u)) ? (kZ ? F[2][q] * z[2][q] : F[2][q]) : T(0);
+        S.u[s][jj][ii] = (kin && (m & 1u)) ? (kZ ? val[0][q] * z[0][q] : val[0][q]) : T(0);
+        S.v[s][jj][ii] = (kin && (m & 2u)) ? (kZ ? val[1][q] * z[1][q] : val[1][q]) : T(0);
+        S.w[s][jj][ii] = (kw && (m & 4u)) ? (kZ ? val[2][q] * z[2][q] : val[2][q]) : T(0);
       }
     }
   };
@@ -356,8 +432,9 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const T dt = (dv[r][c] + op.eta * T(ncell[c])) * op.ih2;
-        sc[r][c] = (MODE == kJacobi || MODE == kJacobiDot || MODE == kJacobiZ) ? omega * recip(dt)
-                                                                               : recip(dt);
+        sc[r][c] = (MODE == kJacobi || MODE == kJacobiDot || MODE == kJacobiZ || MODE == kJacobiP)
+                       ? omega * recip(dt)
+                       : recip(dt);
       }
     }
   };
