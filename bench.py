@@ -58,7 +58,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-COUNTERS_MD = os.path.join(ROOT, "profiles", "tile3d_jacobi_fp32_128cube_counters.md")
+COUNTERS_MD = os.path.join(ROOT, "profiles", "tile3d_jacobi_prolong_fp32_128cube_counters.md")
 KERNEL_SOURCES = ("paper_2001_10424_amd/csrc/tile3d.hpp", "paper_2001_10424_amd/csrc/mac.hpp",
                   "paper_2001_10424_amd/csrc/kernels.hpp")
 
@@ -88,6 +88,18 @@ def counter_traffic():
         return int(float(fields["traffic_bytes_per_launch"]))
     except (OSError, KeyError, ValueError):
         return None
+
+
+def coarse_faces(grid):
+    """Full-face count of the next coarser multigrid level (every axis halved)."""
+    nc = [n // 2 for n in grid.n[:grid.dim]]
+    total = 0
+    for c in range(grid.dim):
+        m = 1
+        for a in range(grid.dim):
+            m *= nc[a] + (a == c)
+        total += m
+    return total
 
 
 def make_solver(gk, pr, mode, net=None):
@@ -236,8 +248,9 @@ def main():
         # dominant kernel on the buffers of one inner solve
         s = make_solver(gk, pr, "mixed_mg")
         s.inner_solve(g, 1e-3)
-        ms = s.time_kernel("smooth", 20)
-        print(json.dumps({"kernel_only": True, "smooth_avg_ms": ms, "m_full": s.m_full}))
+        ms = s.time_kernel("smooth_prolong", 20)
+        print(json.dumps({"kernel_only": True, "smooth_prolong_avg_ms": ms, "m_full": s.m_full,
+                          "m_full_coarse": coarse_faces(pr.grid)}))
         s.close()
         return
 
@@ -258,18 +271,20 @@ def main():
             s2.close()
             log(f"[bench] {m}: {json.dumps(res2)}")
 
-    # dominant kernel: the finest-grid weighted-Jacobi sweep of the inner
-    # solve, k_tile3d<T, false, kJacobi, true> (reads x and b, writes y: three
-    # full-face vectors per launch)
+    # dominant HBM-bound kernel: the finest grid's first post-smoothing sweep
+    # of the V-cycle, k_tile3d<T, false, kJacobiP, true>, which adds the
+    # prolongated coarse correction while staging (reads x, b and the coarse
+    # correction e, writes y: three full-face vectors + one coarse one)
     elem = 4 if MODES[args.mode][0] == "mixed" else 8
-    ms = s.time_kernel("smooth", 100)
-    bytes_per_launch = 3 * s.m_full * elem
+    ms = s.time_kernel("smooth_prolong", 100)
+    bytes_per_launch = (3 * s.m_full + coarse_faces(pr.grid)) * elem
     achieved = bytes_per_launch / (ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": counter_traffic() if elem == 4 else None,
-                "kernel": "k_tile3d<float,false,kJacobi,fine> (finest-grid Jacobi sweep)"
-                if elem == 4 else "k_tile3d<double,false,kJacobi,fine>",
+                "kernel": "k_tile3d<float,false,kJacobiP,fine> (finest-grid post-smoothing "
+                "sweep with the prolongated coarse correction)"
+                if elem == 4 else "k_tile3d<double,false,kJacobiP,fine>",
                 "avg_ms": round(ms, 5), "bytes_per_launch": bytes_per_launch}
     s.close()
 

@@ -222,6 +222,13 @@ int gkb_residual(gkb_ctx *c, const double *g, const double *r, const double *w,
                                 on the finest grid (reads x, b; writes y) */
 #define GKB_KERNEL_APPLY 1   /* y = M x with the fused x.y block partials */
 #define GKB_KERNEL_RESID 2   /* y = b - M x */
+#define GKB_KERNEL_SMOOTH_PROLONG 3  /* the V-cycle's first post-smoothing sweep:
+                                        y = x' + omega D^-1 (b - M x'), x' = x + P e
+                                        with e on the next coarser level (reads x,
+                                        b and e; writes y) */
+#define GKB_KERNEL_SMOOTH_ZERO 4     /* the V-cycle's first two pre-smoothing sweeps
+                                        from a zero guess in one pass (reads b;
+                                        writes y); constant viscosity only */
 
 /* Launch one finest-grid kernel of the inner solver `reps` times back to
    back on the context's stream (working precision of the inner solve, on
@@ -229,8 +236,10 @@ int gkb_residual(gkb_ctx *c, const double *g, const double *r, const double *w,
    graph and replayed, as the solver replays its PCG iterations) and return
    the average time per launch in milliseconds, measured with HIP events
    recorded on that stream around the replay.  Needs
-   inner = GKB_INNER_MG or GKB_INNER_LEARNED.  Does not change solver state
-   other than scratch vectors. */
+   inner = GKB_INNER_MG or GKB_INNER_LEARNED; the two V-cycle sweeps need a
+   3D grid on the tiled path (upper sides DIRICHLET, face arrays below 2 GiB)
+   and a multigrid hierarchy of at least two levels, else GKB_EINVAL.  Does
+   not change solver state other than scratch vectors. */
 int gkb_time_kernel(gkb_ctx *c, int kernel, int reps, double *avg_ms);
 
 #ifdef __cplusplus

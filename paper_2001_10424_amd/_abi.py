@@ -14,7 +14,7 @@ DIRICHLET, NATURAL = 0, 1
 FP64, MIXED = 0, 1
 INNER = {"jacobi": 0, "mg": 1, "learned": 2}
 OPS = {"W": 0, "A": 1, "AT": 2, "M": 3, "diag": 4}
-KERNELS = {"smooth": 0, "apply": 1, "resid": 2}
+KERNELS = {"smooth": 0, "apply": 1, "resid": 2, "smooth_prolong": 3, "smooth_zero": 4}
 SMOOTHERS = {"jacobi": 0, "hybrid": 1}
 
 class Grid(C.Structure):

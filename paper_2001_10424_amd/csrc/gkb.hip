@@ -1392,12 +1392,21 @@ template <typename T>
 int time_kernel_impl(gkb_ctx* c, Inner<T>& in, int kernel, int reps, double* avg_ms) {
   if (!in.ready || reps < 1) return GKB_EINVAL;
   Level<T>& L = in.lv[0];
+  if ((kernel == GKB_KERNEL_SMOOTH_PROLONG || kernel == GKB_KERNEL_SMOOTH_ZERO) &&
+      (!L.fl.tiled || c->L < 2))
+    return GKB_EINVAL;
+  if (kernel == GKB_KERNEL_SMOOTH_ZERO && L.op.mu != nullptr) return GKB_EINVAL;
   hipEvent_t e0, e1;
   HIPCK(hipEventCreate(&e0));
   HIPCK(hipEventCreate(&e1));
   auto one = [&]() {
     if (kernel == GKB_KERNEL_SMOOTH)
       face_op<T, kJacobi>(c, L.op, L.fl, in.z, in.r, L.t, T(L.omega), nullptr, nullptr);
+    else if (kernel == GKB_KERNEL_SMOOTH_PROLONG)
+      face_op<T, kJacobiP>(c, L.op, L.fl, in.z, in.r, L.t, T(L.omega), nullptr, nullptr,
+                           in.lv[1].x, &in.lv[1].g);
+    else if (kernel == GKB_KERNEL_SMOOTH_ZERO)
+      face_op<T, kJacobiZ>(c, L.op, L.fl, in.r, in.r, L.t, T(L.omega), nullptr, nullptr);
     else if (kernel == GKB_KERNEL_APPLY)
       face_op<T, kApplyDot>(c, L.op, L.fl, in.p, nullptr, in.q, T(0), c->part[0], nullptr);
     else
@@ -1431,7 +1440,7 @@ int time_kernel_impl(gkb_ctx* c, Inner<T>& in, int kernel, int reps, double* avg
 }  // namespace
 
 extern "C" int gkb_time_kernel(gkb_ctx* c, int kernel, int reps, double* avg_ms) {
-  if (!c || !avg_ms || kernel < 0 || kernel > 2 || c->opt.inner == GKB_INNER_JACOBI) return GKB_EINVAL;
+  if (!c || !avg_ms || kernel < 0 || kernel > 4 || c->opt.inner == GKB_INNER_JACOBI) return GKB_EINVAL;
   if (c->opt.precision == GKB_MIXED) return time_kernel_impl<float>(c, c->in32, kernel, reps, avg_ms);
   return time_kernel_impl<double>(c, c->in64, kernel, reps, avg_ms);
 }

@@ -156,6 +156,31 @@ __device__ __forceinline__ int axis_count(bool lo_in, bool hi_in, bool lo_wall, 
   return (lo_in ? 1 : (lo_wall ? 2 : 0)) + (hi_in ? 1 : (hi_wall ? 2 : 0));
 }
 
+// Diagonal of M times h^2 (the caller applies 1/h^2) at
+// the face (component c; i, j, k) for constant viscosity, branch-free: the
+// viscous counts of the normal and the two tangential axes (tangential ones
+// halved on a boundary-normal face) plus eta times the number of valid
+// adjacent cells; (pi, pj, pk) is the pinned cell.
+template <typename T>
+__device__ __forceinline__ T diag_const(const Grid& G, T eta, int c, int i, int j, int k, int pi,
+                                        int pj, int pk) {
+  const int n0 = G.n[0], n1 = G.n[1], n2 = G.n[2];
+  const int cx = axis_count(i > 0, i < n0 - 1, G.bc[0] == kDir, G.bc[1] == kDir);
+  const int cy = axis_count(j > 0, j < n1 - 1, G.bc[2] == kDir, G.bc[3] == kDir);
+  const int cz = axis_count(k > 0, k < n2 - 1, G.bc[4] == kDir, G.bc[5] == kDir);
+  const int P = c == 0 ? i : (c == 1 ? j : k), N = c == 0 ? n0 : (c == 1 ? n1 : n2);
+  const int normal = int(P > 0) + int(P < N);
+  const int tang = c == 0 ? cy + cz : (c == 1 ? cx + cz : cx + cy);
+  const T wgt = (P == 0 || P == N) ? T(0.5) : T(1);
+  // adjacent cells along the normal: (i, j, k) and the one below it
+  const bool at_pin = i == pi && j == pj && k == pk;
+  const bool below_pin = (c == 0 ? (i - 1 == pi && j == pj && k == pk)
+                                 : (c == 1 ? (i == pi && j - 1 == pj && k == pk)
+                                           : (i == pi && j == pj && k - 1 == pk)));
+  const int cnt = int(P < N && !at_pin) + int(P > 0 && !below_pin);
+  return T(normal) + wgt * T(tang) + eta * T(cnt);
+}
+
 // FINE only separates the finest-grid launches from the coarse-level ones in
 // kernel traces; the code is the same.
 //
@@ -286,7 +311,11 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
         F.c[2][q] = buf_load<T>(rc, pcv[q], sv);
         F.c[3][q] = buf_load<T>(rc, pcv[q] + rowv, sv);
         F.c[4][q] = buf_load<T>(rc, pcv[q], sw);
-        F.c[5][q] = buf_load<T>(rc, pcv[q], sw1);
+      }
+      // the coarse plane above is needed by the w faces of odd planes only
+      if (kk & 1) {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) F.c[5][q] = buf_load<T>(rc, pcv[q], sw1);
       }
     }
   };
@@ -310,10 +339,7 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
     const int jj = e / kLX, ii = e - jj * kLX;
     const int i = i0 - 1 + ii, j = j0 - 1 + jj;
     if (!((hmask >> (3 * q + c)) & 1u)) return T(0);  // not staged: any value
-    const T d = c == 0   ? diag_M<T, 3, false, 0>(op, i, j, k)
-                : c == 1 ? diag_M<T, 3, false, 1>(op, i, j, k)
-                         : diag_M<T, 3, false, 2>(op, i, j, k);
-    return omega * recip(d);
+    return omega * recip(diag_const<T>(G, op.eta, c, i, j, k, pi, pj, pk) * op.ih2);
   };
   int zb = -1;
   T zs[3][kPer];
