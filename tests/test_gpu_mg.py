@@ -234,9 +234,10 @@ def test_refinement_stops_when_a_sweep_does_not_reduce_the_residual():
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
 def test_time_kernel_replays_and_leaves_the_solver_usable(prec):
-    """gkb_time_kernel (graph replay of the finest-grid sweep, apply and
-    residual kernels) returns a positive time per launch, can be called
-    repeatedly, and the next solve gives bitwise the same result as before."""
+    """gkb_time_kernel (graph replay of the finest-grid sweep, apply,
+    residual and the two fused V-cycle sweeps) returns a positive time per
+    launch, can be called repeatedly, and the next solve gives bitwise the
+    same result as before."""
     _say("time kernel", prec)
     torch = __import__("torch")
     gk = _gk()
@@ -246,7 +247,7 @@ def test_time_kernel_replays_and_leaves_the_solver_usable(prec):
     g, r = _dev(pr.g), _dev(pr.r)
     w0, p0, _ = s.solve(g, r, tol=1e-3, delay=2)
     w0, p0 = w0.clone(), p0.clone()
-    for k in ("smooth", "apply", "resid", "smooth"):
+    for k in ("smooth", "apply", "resid", "smooth_prolong", "smooth_zero", "smooth"):
         ms = s.time_kernel(k, 10)
         assert 0.0 < ms < 50.0, (k, ms)
     w1, p1, _ = s.solve(g, r, tol=1e-3, delay=2)
