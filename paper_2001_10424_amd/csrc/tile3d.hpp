@@ -15,6 +15,12 @@
 // divergence of its cell below in registers.  Global traffic per plane is one
 // pass over the tile (+ halo, mostly L2 hits) of x, plus b and y for the
 // faces the block owns.
+//
+// Two modes transform the values while they are staged, so that a V-cycle
+// step needs no separate pass over memory: kJacobiZ stages x1 = omega b / D
+// (the first sweep from a zero guess; the kernel then applies the second),
+// and kJacobiP stages x + P e, the prolongation of the coarse-grid
+// correction e.
 #pragma once
 #include "kernels.hpp"
 
