@@ -70,6 +70,9 @@ TILED_CASES = MG_CASES[:2] + [
     ("3d_lower_natural_const", P.Grid(3, (16, 24, 16), 1 / 16, (N, D, N, D, D, D), -1), 10.0,
      False),
     ("3d_pin_mid", P.Grid(3, (16, 8, 12), 1 / 8, (D,) * 6, 5 * 16 * 8 + 3 * 16 + 7), 1e2, False),
+    # two planes per tiled block, the pinned cell on the second plane of a block
+    ("3d_tz2_pin", P.Grid(3, (128, 128, 32), 1 / 128, (D,) * 6, 5 * 128 * 128 + 70 * 128 + 33),
+     1e2, False),
 ]
 
 
