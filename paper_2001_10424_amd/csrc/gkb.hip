@@ -93,10 +93,11 @@ FaceLaunch face_launch(const Grid& g, int kz, int stencil = 0) {
     }
     L.tiled = true;
     const int tx = (g.n[0] + kTX - 1) / kTX, ty = (g.n[1] + kTY - 1) / kTY;
-    // z-planes per block: keep >= ~1024 blocks in flight (4 per CU); more
-    // planes per block amortise the z-halo and the block set-up but starve
-    // small grids (128^3: 8 planes, 1024 blocks; 2, 4 and 16 were slower)
-    int tz = g_tz > 0 ? g_tz : std::max(1, std::min(8, tx * ty * g.n[2] / 1024));
+    // z-planes per block: keep >= ~512 blocks in flight; more planes per
+    // block amortise the z-halo and the block set-up but starve small grids
+    // (128^3: 8 planes, 1024 blocks, where 2, 4 and 16 were slower; 64^3: 2
+    // planes, 512 blocks, 1-3 % faster MG-PCG iterations than 1 or 4)
+    int tz = g_tz > 0 ? g_tz : std::max(1, std::min(8, tx * ty * g.n[2] / 512));
     L.tz = std::min(tz, g.n[2]);
     L.tgrid = dim3(tx, ty, (g.n[2] + L.tz - 1) / L.tz);
     L.nparts = L.tgrid.x * L.tgrid.y * L.tgrid.z;
