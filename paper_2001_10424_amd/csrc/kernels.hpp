@@ -87,9 +87,12 @@ enum MMode {
   kJacobiZ = 9,    // two sweeps from a zero guess: y = x1 + omega (b - M x1) / D
                    // with x1 = omega b / D (x1 formed while staging; tiled
                    // kernel, constant viscosity only; x = b)
-  kJacobiP = 10    // sweep after the coarse-grid correction: y = x' + omega
+  kJacobiP = 10,   // sweep after the coarse-grid correction: y = x' + omega
                    // (b - M x') / D with x' = x + P e (prolongation of the
                    // coarse correction e added while staging; tiled kernel)
+  kApplyDotP = 11  // CG direction update and product in one pass: p' = x + beta
+                   // p (x = z, b = p, beta from the PCG state) formed while
+                   // staging, y = M p', p' written to y2, partial p'.y
 };
 
 // Thread mapping: blockIdx.z = component * zchunks + z-chunk; each block

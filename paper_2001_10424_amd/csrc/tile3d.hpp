@@ -111,12 +111,13 @@ constexpr bool reads_b() {
 // the result goes to byte offset voff + soff of y
 template <typename T, int MODE>
 __device__ __forceinline__ double tile_finish(unsigned voff, unsigned soff, bool unk, T mx, T d,
-                                              T xf, T bf, __amdgpu_buffer_rsrc_t ry, T omega) {
+                                              T xf, T bf, __amdgpu_buffer_rsrc_t ry, T omega,
+                                              __amdgpu_buffer_rsrc_t ry2) {
   double part = 0.0;
   T out;
-  if (MODE == kApply || MODE == kApplyDot) {
+  if (MODE == kApply || MODE == kApplyDot || MODE == kApplyDotP) {
     out = unk ? mx : T(0);
-    if (MODE == kApplyDot) part = double(xf) * double(out);
+    if (MODE == kApplyDot || MODE == kApplyDotP) part = double(xf) * double(out);
   } else if (MODE == kJacobi || MODE == kJacobiDot || MODE == kJacobiZ || MODE == kJacobiP) {
     out = unk ? xf + omega * (bf - mx) * recip(d) : T(0);
     if (MODE == kJacobiDot) part = double(bf) * double(out);
@@ -128,6 +129,7 @@ __device__ __forceinline__ double tile_finish(unsigned voff, unsigned soff, bool
     part = double(out) * double(out);
   }
   buf_store(out, ry, voff, soff);
+  if (MODE == kApplyDotP) buf_store(unk ? xf : T(0), ry2, voff, soff);  // p'
   return part;
 }
 
@@ -136,12 +138,13 @@ __device__ __forceinline__ double tile_finish(unsigned voff, unsigned soff, bool
 // kDinvM, unused otherwise).
 template <typename T, int MODE>
 __device__ __forceinline__ double tile_out(unsigned voff, unsigned soff, bool unk, T mx, T sc,
-                                           T xf, T bf, __amdgpu_buffer_rsrc_t ry) {
+                                           T xf, T bf, __amdgpu_buffer_rsrc_t ry,
+                                           __amdgpu_buffer_rsrc_t ry2) {
   double part = 0.0;
   T out;
-  if (MODE == kApply || MODE == kApplyDot) {
+  if (MODE == kApply || MODE == kApplyDot || MODE == kApplyDotP) {
     out = unk ? mx : T(0);
-    if (MODE == kApplyDot) part = double(xf) * double(out);
+    if (MODE == kApplyDot || MODE == kApplyDotP) part = double(xf) * double(out);
   } else if (MODE == kJacobi || MODE == kJacobiDot || MODE == kJacobiZ || MODE == kJacobiP) {
     out = unk ? xf + (bf - mx) * sc : T(0);
     if (MODE == kJacobiDot) part = double(bf) * double(out);
@@ -153,6 +156,7 @@ __device__ __forceinline__ double tile_out(unsigned voff, unsigned soff, bool un
     part = double(out) * double(out);
   }
   buf_store(out, ry, voff, soff);
+  if (MODE == kApplyDotP) buf_store(unk ? xf : T(0), ry2, voff, soff);  // p'
   return part;
 }
 
@@ -210,7 +214,8 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
                                                 const T* __restrict__ b, T* __restrict__ y,
                                                 T omega, int tz, double* __restrict__ partial,
                                                 const PcgState* __restrict__ st,
-                                                const T* __restrict__ ec, Grid Gc) {
+                                                const T* __restrict__ ec, Grid Gc,
+                                                T* __restrict__ y2) {
   if (st && st->done) return;
   __shared__ TileLds<T> S;
   const Grid& G = op.g;
@@ -268,7 +273,14 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
   // and J+1 unknown.  The coarse values (faces I / I+1, J / J+1, coarse
   // planes K / K+1) are prefetched with the plane.
   constexpr bool kP = MODE == kJacobiP;
-  constexpr int kPC = kP ? 6 : 1;
+  // kApplyDotP: the staged values are p' = z + beta p (x = z, b = p); p is
+  // loaded with z into the second register set, p' is written to y2 at the
+  // block's own faces
+  constexpr bool kAP = MODE == kApplyDotP;
+  constexpr int kPC = kP ? 6 : (kAP ? 3 : 1);
+  const T pbeta = (kAP && st) ? T(st->beta) : T(0);
+  const __amdgpu_buffer_rsrc_t rpo = kAP ? buf_rsrc(b, bytes) : rx;
+  const __amdgpu_buffer_rsrc_t ry2 = kAP ? buf_rsrc(y2, bytes) : ry;
   unsigned pcu[kPer], pcv[kPer], pbits = 0;
   const __amdgpu_buffer_rsrc_t rc = kP ? buf_rsrc(ec, unsigned(Gc.m_full) * E) : rx;
   const unsigned dwc = kP ? unsigned(Gc.off[2] - Gc.off[1]) * E : 0u;
@@ -302,6 +314,14 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
       F.v[0][q] = buf_load<T>(rx, hu[q], unsigned(kk * pu) * E);
       F.v[1][q] = buf_load<T>(rx, hv[q], unsigned(kk * pv) * E);
       F.v[2][q] = buf_load<T>(rx, hv[q], unsigned(kk * pw) * E + dw);
+    }
+    if (kAP) {
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        F.c[0][q] = buf_load<T>(rpo, hu[q], unsigned(kk * pu) * E);
+        F.c[1][q] = buf_load<T>(rpo, hv[q], unsigned(kk * pv) * E);
+        F.c[2][q] = buf_load<T>(rpo, hv[q], unsigned(kk * pw) * E + dw);
+      }
     }
     if (kP) {
       const int K = kk >> 1, K1 = min(K + 1, Gc.ext[2][2] - 1);
@@ -364,7 +384,7 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
 #pragma unroll
     for (int q = 0; q < kPer; ++q)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) val[c][q] = F.v[c][q];
+      for (int c = 0; c < 3; ++c) val[c][q] = kAP ? F.v[c][q] + pbeta * F.c[c][q] : F.v[c][q];
     if (kP && kin) {
       // coarse plane K = k / 2; a w face on an odd plane lies between K and K+1
       const int K = k >> 1;
@@ -580,7 +600,7 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
               d += eta * T(cnt);
             }
             part += tile_finish<T, MODE>(fo[r][0], unsigned(k * pu) * E, i > 0 || unk_u0,
-                                         acc * ih2, d * ih2, xf, bc[r][0], ry, omega);
+                                         acc * ih2, d * ih2, xf, bc[r][0], ry, omega, ry2);
           }
         }
         // ---- v-face (i, j, k): normal y
@@ -611,7 +631,7 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
               d += eta * T(cnt);
             }
             part += tile_finish<T, MODE>(fo[r][1], unsigned(k * pv) * E, j > 0 || unk_v0,
-                                         acc * ih2, d * ih2, xf, bc[r][1], ry, omega);
+                                         acc * ih2, d * ih2, xf, bc[r][1], ry, omega, ry2);
           }
         }
         // ---- w-face (i, j, k): normal z
@@ -641,13 +661,16 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
               d += eta * T(cnt);
             }
             part += tile_finish<T, MODE>(fo[r][1], unsigned(k * pw) * E + dw, k > 0 || unk_w0,
-                                         acc * ih2, d * ih2, xf, bc[r][2], ry, omega);
+                                         acc * ih2, d * ih2, xf, bc[r][2], ry, omega, ry2);
           }
         }
         // upper boundary faces are Dirichlet faces: keep them zero
         if (i == nx - 1) buf_store(T(0), ry, fo[r][0] + E, unsigned(k * pu) * E);
+        if (kAP) { if (i == nx - 1) buf_store(T(0), ry2, fo[r][0] + E, unsigned(k * pu) * E); }
         if (j == ny - 1) buf_store(T(0), ry, fo[r][1] + unsigned(nx) * E, unsigned(k * pv) * E);
+        if (kAP) { if (j == ny - 1) buf_store(T(0), ry2, fo[r][1] + unsigned(nx) * E, unsigned(k * pv) * E); }
         if (k == nz - 1) buf_store(T(0), ry, fo[r][1], unsigned(nz * pw) * E + dw);
+        if (kAP) { if (k == nz - 1) buf_store(T(0), ry2, fo[r][1], unsigned(nz * pw) * E + dw); }
         up[r] = S.u[s][jj][ii];
         vp[r] = S.v[s][jj][ii];
         wp[r] = S.w[s][jj][ii];
@@ -698,8 +721,9 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
                                          (S.w[s][jj - 1][ii] + S.w[s][jj + 1][ii])));
       if (i < nx && j < ny) {
         part += tile_out<T, MODE>(fo[r][1], unsigned(k * pw) * E + dw, k > 0 || unk_w0, aw * ih2,
-                                  sc[r][2], wC, bc[r][2], ry);
+                                  sc[r][2], wC, bc[r][2], ry, ry2);
         if (k == nz - 1) buf_store(T(0), ry, fo[r][1], unsigned(nz * pw) * E + dw);
+        if (kAP) { if (k == nz - 1) buf_store(T(0), ry2, fo[r][1], unsigned(nz * pw) * E + dw); }
       }
       up[r] = uC;
       vp[r] = vC;
@@ -721,13 +745,15 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
       if (i < nx && j < ny) {
         part += tile_out<T, MODE>(fo[r][0], unsigned(k * pu) * E, i > 0 || unk_u0,
                                   (au[r] - eta * S.cd[jj][ii - 1]) * ih2, sc[r][0], up[r],
-                                  bc[r][0], ry);
+                                  bc[r][0], ry, ry2);
         part += tile_out<T, MODE>(fo[r][1], unsigned(k * pv) * E, j > 0 || unk_v0,
                                   (av[r] - eta * S.cd[jj - 1][ii]) * ih2, sc[r][1], vp[r],
-                                  bc[r][1], ry);
+                                  bc[r][1], ry, ry2);
         // upper boundary faces are Dirichlet faces: keep them zero
         if (i == nx - 1) buf_store(T(0), ry, fo[r][0] + E, unsigned(k * pu) * E);
+        if (kAP) { if (i == nx - 1) buf_store(T(0), ry2, fo[r][0] + E, unsigned(k * pu) * E); }
         if (j == ny - 1) buf_store(T(0), ry, fo[r][1] + unsigned(nx) * E, unsigned(k * pv) * E);
+        if (kAP) { if (j == ny - 1) buf_store(T(0), ry2, fo[r][1] + unsigned(nx) * E, unsigned(k * pv) * E); }
       }
     }
     if (!kbulk) coef(0, true);
@@ -744,7 +770,8 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
       if (k + 1 < k1) step_c(k + 1, FB, bB);
     }
   }
-  constexpr bool kRed = MODE == kApplyDot || MODE == kJacobiDot || MODE == kDinvM || MODE == kResidDot;
+  constexpr bool kRed = MODE == kApplyDot || MODE == kJacobiDot || MODE == kDinvM ||
+                        MODE == kResidDot || MODE == kApplyDotP;
   if (kRed) {
     __shared__ double sh[256 / 64];
     double t = block_sum<256>(part, sh);
