@@ -257,3 +257,27 @@ def test_time_kernel_replays_and_leaves_the_solver_usable(prec):
     torch.cuda.synchronize()
     assert torch.equal(w0, w1) and torch.equal(p0, p1)
     s.close()
+
+
+def test_fp32_direction_update_fused_and_separate_agree():
+    """FP32 MG-PCG forms the direction update inside the product when a
+    captured chunk has an even number of iterations and runs the separate
+    update kernel otherwise (odd chunk, 5): the same arithmetic, so the same
+    iteration count and solution; the true residual of an FP32 solve sits at
+    the FP32 level of this grad-div-dominated operator (eta = 1e3), above
+    the recursive residual that stops it."""
+    _say("fp32 direction update")
+    gk = _gk()
+    pr = P.stokes_problem(3, 32, seed=6, eta=1e3)
+    f = _dev(pr.g)
+    out = []
+    for chunk in (8, 5):
+        s = gk.Solver(pr.grid, None, pr.eta, inner="mg", precision="mixed", check_every=chunk)
+        x, it = s.inner_solve(f, 1e-5)
+        r = s.apply("M", x) - f
+        out.append((x.cpu().numpy(), it, float((r * r).sum().sqrt() / (f * f).sum().sqrt())))
+        s.close()
+    (xa, ia, ra), (xb, ib, rb) = out
+    assert ra <= 1e-3 and rb <= 1e-3, (ra, rb)
+    assert ia == ib, (ia, ib)
+    assert _rel(xa, xb) <= 1e-6
