@@ -118,6 +118,9 @@ def test_null_context_calls_fail_cleanly(lib):
     assert lib.gkb_stats(None, C.byref(st)) == _abi.GKB_EINVAL
     assert lib.gkb_solve(None, None, None, 1e-8, 5, None, None, None, None) == _abi.GKB_EINVAL
     lib.gkb_destroy(None)
+    ms = C.c_double()
+    for k in (0, 3, 4, 5, -1):
+        assert lib.gkb_time_kernel(None, k, 10, C.byref(ms)) == _abi.GKB_EINVAL
     bad = C.c_void_p()
     ch = (C.c_int * 3)(4, 40, 3)  # a layer wider than 16 channels
     assert lib.gkb_cnn_create(3, 2, ch, 0, C.byref(bad)) == _abi.GKB_EINVAL
