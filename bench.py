@@ -4,13 +4,15 @@ of 1e-8, on one MI355X.
 
 A step is one complete gkb_solve (transformation, outer GKB recurrence, all
 inner preconditioned solves, FP64 residual checks and defect-correction
-sweeps) on inputs already resident in HBM.  Three solver configurations of
-the same problem are timed:
+sweeps) on inputs already resident in HBM.  Solver configurations of the
+same problem timed:
 
-  mixed_learned  FP32 inner flexible CG with V-cycle + CNN correction
-                 (MG-PCG fallback), FP64 GKB recurrence and residual
-  mixed_mg       FP32 inner MG-PCG, FP64 GKB recurrence and residual
-  fp64_mg        FP64 everywhere (plain multigrid GKB)
+  mixed_learned    FP32 inner flexible CG with V-cycle + CNN correction
+                   (MG-PCG fallback), FP64 GKB recurrence and residual
+  mixed_mg         FP32 inner MG-PCG, FP64 GKB recurrence and residual
+  fp64_mg          FP64 everywhere (plain multigrid GKB)
+  fp64_gkb1        FP64, one GKB run to the target (no defect correction)
+  *_mg_hybrid      FP64 / FP32 inner MG-PCG with the face + edge smoother
 
 `value` is the time of --mode (default mixed_learned); the others are in
 config.compare_seconds.  The CNN of the learned mode is trained first on
