@@ -41,7 +41,8 @@ class _GkbOpts(C.Structure):
                 ("squared_rule", C.c_int),
                 ("zeta", C.c_void_p), ("alpha", C.c_void_p), ("beta", C.c_void_p),
                 ("est_hist", C.c_void_p), ("inner_iters", C.c_void_p),
-                ("store_k", C.c_int), ("V", C.c_void_p), ("Q", C.c_void_p)]
+                ("store_k", C.c_int), ("V", C.c_void_p), ("Q", C.c_void_p),
+                ("inner_krylov", C.c_int), ("restart", C.c_int)]
 
 
 _lib = None
@@ -73,6 +74,16 @@ def lib():
                                    C.POINTER(C.c_int)]
         L.og_gkb_solve.restype = C.c_int
         L.og_saddle_residual.argtypes = [G, P, P, P, P, P, P, P, P]
+        L.og_gkb_fgmres.argtypes = [G, P, C.c_double, P, P, C.POINTER(_GkbOpts), C.c_double,
+                                    C.c_int, C.c_int, P, P, C.POINTER(C.c_int),
+                                    C.POINTER(C.c_int)]
+        L.og_gkb_fgmres.restype = C.c_int
+        L.og_csr_central_scaling.argtypes = [C.c_int, C.c_int] + [P] * 8
+        L.og_csr_central_scaling.restype = C.c_int
+        L.og_gkb_solve_csr.argtypes = [C.c_int, C.c_int] + [P] * 6 + [C.c_double, C.c_int, P, P,
+                                       C.POINTER(_GkbOpts), P, P, C.POINTER(C.c_int),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_int)]
+        L.og_gkb_solve_csr.restype = C.c_int
         _lib = L
     return _lib
 
@@ -168,11 +179,13 @@ def pcg(grid, f, eta, mu=None, tol=1e-12, maxit=100000):
 
 
 def gkb_solve(grid, g, r, eta, mu=None, tol=1e-8, delay=5, maxit=1000,
-              inner_tol=1e-12, inner_maxit=100000, squared_rule=False, store_k=0):
-    """Generalized GKB (Algorithm 1) with the transformation to g = 0 and a
-    Jacobi-PCG inner solve.  Returns a dict with w, p, status, K, est and the
-    per-step histories (zeta, alpha, beta, est_hist, inner_iters); with
-    store_k > 0 also the first store_k columns of V and Q."""
+              inner_tol=1e-12, inner_maxit=100000, squared_rule=False, store_k=0,
+              krylov="cg", restart=30):
+    """Generalized GKB (Section 2.1) with the transformation to g = 0 and a
+    Jacobi-preconditioned inner solve (krylov "cg", or "fgmres" with the given
+    restart).  Returns a dict with w, p, status, K, est and the per-step
+    histories (zeta, alpha, beta, est_hist, inner_iters); with store_k > 0
+    also the first store_k columns of V and Q."""
     gs = _grid(grid)
     g, r, mu = _f64(g), _f64(r), _f64(mu)
     m, n = sizes(grid)
@@ -190,7 +203,8 @@ def gkb_solve(grid, g, r, eta, mu=None, tol=1e-8, delay=5, maxit=1000,
                  squared_rule=int(bool(squared_rule)),
                  zeta=zeta.ctypes.data, alpha=alpha.ctypes.data, beta=beta.ctypes.data,
                  est_hist=est_hist.ctypes.data, inner_iters=inner.ctypes.data,
-                 store_k=int(store_k), V=V.ctypes.data, Q=Q.ctypes.data)
+                 store_k=int(store_k), V=V.ctypes.data, Q=Q.ctypes.data,
+                 inner_krylov={"cg": 0, "fgmres": 1}[krylov], restart=int(restart))
     K = C.c_int(0)
     est = C.c_double(0.0)
     tot = C.c_int(0)
@@ -203,6 +217,80 @@ def gkb_solve(grid, g, r, eta, mu=None, tol=1e-8, delay=5, maxit=1000,
                 est_hist=est_hist[:k].copy(), inner_iters=inner[:k + 1].copy(),
                 V=V[:min(store_k, k)].copy() if store_k else None,
                 Q=Q[:min(store_k, k)].copy() if store_k else None)
+
+
+def gkb_fgmres(grid, g, r, eta, mu=None, tol=1e-8, restart=10, maxit=50, gkb_tol=1e-2,
+               delay=2, gkb_maxit=200, inner_tol=1e-12, inner_maxit=100000, krylov="cg",
+               inner_restart=30):
+    """GKB as a preconditioner (Section 3): flexible GMRES on the saddle
+    system, right preconditioned by one GKB run (lower-bound tolerance
+    gkb_tol, delay, gkb_maxit; Jacobi-preconditioned inner solves), stopped at
+    the relative residual tol.  Returns a dict with w, p, status, iterations
+    (outer steps = GKB runs) and inner_total."""
+    gs = _grid(grid)
+    g, r, mu = _f64(g), _f64(r), _f64(mu)
+    m, n = sizes(grid)
+    w = np.empty(m)
+    p = np.empty(n)
+    o = _GkbOpts(tol=float(gkb_tol), delay=int(delay), maxit=int(gkb_maxit),
+                 inner_tol=float(inner_tol), inner_maxit=int(inner_maxit), squared_rule=0,
+                 store_k=0, inner_krylov={"cg": 0, "fgmres": 1}[krylov],
+                 restart=int(inner_restart))
+    it = C.c_int(0)
+    tot = C.c_int(0)
+    st = lib().og_gkb_fgmres(C.byref(gs), _ptr(mu), float(eta), _ptr(g), _ptr(r), C.byref(o),
+                             float(tol), int(restart), int(maxit), _ptr(w), _ptr(p),
+                             C.byref(it), C.byref(tot))
+    return dict(w=w, p=p, status=st, iterations=it.value, inner_total=tot.value)
+
+
+def _csr_parts(M):
+    """(rowptr int32, col int32, val float64) of a scipy.sparse matrix."""
+    M = M.tocsr()
+    M.sort_indices()
+    return (np.ascontiguousarray(M.indptr, dtype=np.int32),
+            np.ascontiguousarray(M.indices, dtype=np.int32),
+            np.ascontiguousarray(M.data, dtype=np.float64))
+
+
+def csr_central_scaling(W, A):
+    """Central scaling vectors (s_w, s_p) = (diag(W)^-1/2, diag(A^T diag(W)^-1
+    A)^-1/2) of CSR blocks W, A (scipy.sparse)."""
+    m, n = A.shape
+    wp, wc, wv = _csr_parts(W)
+    ap, ac, av = _csr_parts(A)
+    sw, sp = np.empty(m), np.empty(n)
+    st = lib().og_csr_central_scaling(m, n, _ptr(wp), _ptr(wc), _ptr(wv), _ptr(ap), _ptr(ac),
+                                      _ptr(av), _ptr(sw), _ptr(sp))
+    if st != OK:
+        raise ValueError("central scaling needs diag(W) > 0 and no empty column of A")
+    return sw, sp
+
+
+def gkb_solve_csr(W, A, g, r, eta, scaling=False, tol=1e-8, delay=5, maxit=1000,
+                  inner_tol=1e-12, inner_maxit=100000, krylov="cg", restart=30):
+    """GKB on the assembled saddle system with CSR blocks W (m x m) and A
+    (m x n) (scipy.sparse), optionally with central scaling (Section 4.1).
+    Returns a dict like gkb_solve."""
+    m, n = A.shape
+    wp, wc, wv = _csr_parts(W)
+    ap, ac, av = _csr_parts(A)
+    g, r = _f64(g), _f64(r)
+    w, p = np.empty(m), np.empty(n)
+    zeta = np.zeros(maxit)
+    inner = np.zeros(maxit + 1, dtype=np.int32)
+    o = _GkbOpts(tol=float(tol), delay=int(delay), maxit=int(maxit),
+                 inner_tol=float(inner_tol), inner_maxit=int(inner_maxit), squared_rule=0,
+                 zeta=zeta.ctypes.data, inner_iters=inner.ctypes.data, store_k=0,
+                 inner_krylov={"cg": 0, "fgmres": 1}[krylov], restart=int(restart))
+    K, est, tot = C.c_int(0), C.c_double(0.0), C.c_int(0)
+    st = lib().og_gkb_solve_csr(m, n, _ptr(wp), _ptr(wc), _ptr(wv), _ptr(ap), _ptr(ac),
+                                _ptr(av), float(eta), int(bool(scaling)), _ptr(g), _ptr(r),
+                                C.byref(o), _ptr(w), _ptr(p), C.byref(K), C.byref(est),
+                                C.byref(tot))
+    k = K.value
+    return dict(w=w, p=p, status=st, K=k, est=est.value, inner_total=tot.value,
+                zeta=zeta[:k].copy(), inner_iters=inner[:k + 1].copy())
 
 
 def saddle_residual(grid, g, r, w, p, mu=None):

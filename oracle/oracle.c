@@ -335,19 +335,103 @@ static int all_zero(long n, const double *a) {
   return 1;
 }
 
-/* ------------------------------------------------------ Jacobi-PCG on M */
+/* ------------------------------------------------------ operator bundle */
+
+/* The GKB iteration and its inner solvers see the saddle system only through
+   the products with W, A and A^T, the diagonal of M and the masks of the
+   unknowns, so the same code serves the matrix-free MAC operators and
+   assembled (CSR) matrices. */
+typedef struct og_ops og_ops;
+struct og_ops {
+  long m, n;           /* lengths of the velocity and pressure arrays */
+  double eta;          /* M = W + eta A A^T (eta = 0: M = W) */
+  const void *data;    /* operator-specific data */
+  void (*W)(const og_ops *o, const double *x, double *y);
+  void (*A)(const og_ops *o, const double *p, double *y);
+  void (*AT)(const og_ops *o, const double *x, double *t);
+  void (*diag_M)(const og_ops *o, double *d);
+  const double *mask_m; /* 1 on unknown velocity entries, 0 elsewhere */
+  const double *mask_n; /* 1 on unknown pressure entries, 0 elsewhere */
+};
+
+static void ops_M(const og_ops *o, const double *x, double *y) {
+  o->W(o, x, y);
+  if (o->eta == 0.0) return;
+  double *t = malloc(sizeof(double) * o->n), *z = malloc(sizeof(double) * o->m);
+  o->AT(o, x, t);
+  o->A(o, t, z);
+  for (long f = 0; f < o->m; ++f) y[f] += o->eta * z[f];
+  free(t);
+  free(z);
+}
+
+/* the MAC operators as a bundle */
+typedef struct {
+  const og_grid *g;
+  const double *mu;
+} mac_data;
+
+static void mac_W(const og_ops *o, const double *x, double *y) {
+  const mac_data *d = o->data;
+  og_apply_W(d->g, d->mu, x, y);
+}
+static void mac_A(const og_ops *o, const double *p, double *y) {
+  og_apply_A(((const mac_data *)o->data)->g, p, y);
+}
+static void mac_AT(const og_ops *o, const double *x, double *t) {
+  og_apply_AT(((const mac_data *)o->data)->g, x, t);
+}
+static void mac_diag(const og_ops *o, double *d) {
+  const mac_data *md = o->data;
+  og_diag_M(md->g, md->mu, o->eta, d);
+}
+
+/* fills *o for the MAC grid; the masks are allocated (free with
+   mac_ops_free) */
+static int mac_ops(og_ops *o, mac_data *md, const og_grid *g, const double *mu, double eta) {
+  md->g = g;
+  md->mu = mu;
+  o->m = og_m_full(g);
+  o->n = og_n_cells(g);
+  o->eta = eta;
+  o->data = md;
+  o->W = mac_W;
+  o->A = mac_A;
+  o->AT = mac_AT;
+  o->diag_M = mac_diag;
+  double *mm = malloc(sizeof(double) * o->m), *mn = malloc(sizeof(double) * o->n);
+  if (!mm || !mn) {
+    free(mm);
+    free(mn);
+    return OG_ENOMEM;
+  }
+  /* unknown faces: the diagonal of W is positive exactly there */
+  og_diag_M(g, mu, 0.0, mm);
+  for (long i = 0; i < o->m; ++i) mm[i] = mm[i] > 0.0 ? 1.0 : 0.0;
+  for (long i = 0; i < o->n; ++i) mn[i] = (i == g->pin) ? 0.0 : 1.0;
+  o->mask_m = mm;
+  o->mask_n = mn;
+  return OG_OK;
+}
+
+static void mac_ops_free(og_ops *o) {
+  free((void *)o->mask_m);
+  free((void *)o->mask_n);
+}
+
+/* ------------------------------------------------------ inner solvers */
 
 /* Solve M x = f by CG with the Jacobi preconditioner diag(M)^-1, x0 = 0.
    Stops when ||f - M x_i||_2 <= tol ||f||_2 (recursive residual) or after
    maxit iterations.  Returns OG_OK or OG_EINNER; *iters = iterations done. */
-int og_pcg(const og_grid *g, const double *mu, double eta, const double *f,
-           double *x, double tol, int maxit, int *iters) {
-  long mf = og_m_full(g);
+static int pcg_ops(const og_ops *o, const double *f, double *x, double tol, int maxit,
+                   int *iters) {
+  long mf = o->m;
   double *r = malloc(sizeof(double) * mf), *z = malloc(sizeof(double) * mf);
   double *p = malloc(sizeof(double) * mf), *q = malloc(sizeof(double) * mf);
   double *dg = malloc(sizeof(double) * mf);
   if (!r || !z || !p || !q || !dg) return OG_ENOMEM;
-  og_diag_M(g, mu, eta, dg);
+  o->diag_M(o, dg);
   for (long i = 0; i < mf; ++i) {
     x[i] = 0.0;
     r[i] = f[i];
@@ -359,7 +443,7 @@ int og_pcg(const og_grid *g, const double *mu, double eta, const double *f,
   int it = 0, status = OG_EINNER;
   if (rr0 == 0.0) status = OG_OK;
   while (status != OG_OK && it < maxit) {
-    og_apply_M(g, mu, eta, p, q);
+    ops_M(o, p, q);
     double pq = dot(mf, p, q);
     double alpha = rz / pq;
     for (long i = 0; i < mf; ++i) {
@@ -391,13 +475,112 @@ int og_pcg(const og_grid *g, const double *mu, double eta, const double *f,
   return status;
 }
 
+int og_pcg(const og_grid *g, const double *mu, double eta, const double *f, double *x,
+           double tol, int maxit, int *iters) {
+  og_ops o;
+  mac_data md;
+  if (mac_ops(&o, &md, g, mu, eta) != OG_OK) return OG_ENOMEM;
+  int st = pcg_ops(&o, f, x, tol, maxit, iters);
+  mac_ops_free(&o);
+  return st;
+}
+
+/* Flexible GMRES (Saad 1993) for M x = f, x0 = 0, restarted after `restart`
+   steps, with the Jacobi preconditioner applied on the right: z_j =
+   diag(M)^-1 v_j, basis vectors from M z_j orthogonalised by modified
+   Gram-Schmidt, Givens rotations on the Hessenberg matrix, x += Z y at the
+   end of a cycle (early when the residual norm of the least-squares problem
+   is <= tol ||f||) and a restart from the true residual.  Stops when the
+   true residual at the end of a cycle is <= tol ||f||, or after maxit steps
+   (OG_EINNER). */
+static int fgmres_ops(const og_ops *o, const double *f, double *x, double tol, int restart,
+                      int maxit, int *iters) {
+  long mf = o->m;
+  int R = restart;
+  double *V = malloc(sizeof(double) * mf * (R + 1)), *Z = malloc(sizeof(double) * mf * R);
+  double *H = calloc((size_t)(R + 1) * R, sizeof(double));
+  double *cs = malloc(sizeof(double) * R), *sn = malloc(sizeof(double) * R);
+  double *gv = malloc(sizeof(double) * (R + 1)), *y = malloc(sizeof(double) * R);
+  double *dg = malloc(sizeof(double) * mf), *r = malloc(sizeof(double) * mf);
+  if (!V || !Z || !H || !cs || !sn || !gv || !y || !dg || !r) return OG_ENOMEM;
+  o->diag_M(o, dg);
+  for (long i = 0; i < mf; ++i) {
+    x[i] = 0.0;
+    r[i] = f[i];
+  }
+  double ff = dot(mf, f, f);
+  int it = 0, status = OG_EINNER;
+  if (ff == 0.0) status = OG_OK;
+  while (status == OG_EINNER) {
+    double beta = sqrt(dot(mf, r, r));
+    if (!isfinite(beta)) {
+      status = OG_ENAN;
+      break;
+    }
+    if (beta * beta <= tol * tol * ff) {
+      status = OG_OK;
+      break;
+    }
+    if (it >= maxit) break;
+    for (long i = 0; i < mf; ++i) V[i] = r[i] / beta;
+    for (int i = 0; i <= R; ++i) gv[i] = 0.0;
+    gv[0] = beta;
+    int k = 0, conv = 0;
+    for (int j = 0; j < R && it < maxit; ++j) {
+      double *vj = V + (long)j * mf, *zj = Z + (long)j * mf, *w = V + (long)(j + 1) * mf;
+      for (long i = 0; i < mf; ++i) zj[i] = dg[i] > 0.0 ? vj[i] / dg[i] : 0.0;
+      ops_M(o, zj, w);
+      for (int i = 0; i <= j; ++i) {
+        double hij = dot(mf, w, V + (long)i * mf);
+        H[(long)i * R + j] = hij;
+        for (long l = 0; l < mf; ++l) w[l] -= hij * V[(long)i * mf + l];
+      }
+      double hn = sqrt(dot(mf, w, w));
+      for (int i = 0; i < j; ++i) { /* earlier rotations on column j */
+        double a = H[(long)i * R + j], b = H[(long)(i + 1) * R + j];
+        H[(long)i * R + j] = cs[i] * a + sn[i] * b;
+        H[(long)(i + 1) * R + j] = -sn[i] * a + cs[i] * b;
+      }
+      double a = H[(long)j * R + j], rr = sqrt(a * a + hn * hn);
+      ++it;
+      if (rr == 0.0) break; /* M z_j adds nothing: restart */
+      cs[j] = a / rr;
+      sn[j] = hn / rr;
+      H[(long)j * R + j] = rr;
+      gv[j + 1] = -sn[j] * gv[j];
+      gv[j] = cs[j] * gv[j];
+      k = j + 1;
+      if (gv[j + 1] * gv[j + 1] <= tol * tol * ff || hn == 0.0) {
+        conv = 1;
+        break;
+      }
+      for (long l = 0; l < mf; ++l) w[l] /= hn;
+    }
+    for (int i = k - 1; i >= 0; --i) { /* R y = g */
+      double v = gv[i];
+      for (int l = i + 1; l < k; ++l) v -= H[(long)i * R + l] * y[l];
+      y[i] = v / H[(long)i * R + i];
+    }
+    for (int l = 0; l < k; ++l)
+      for (long i = 0; i < mf; ++i) x[i] += y[l] * Z[(long)l * mf + i];
+    /* the true residual decides, also after the estimate met the tolerance
+       (near rounding level the two part) */
+    (void)conv;
+    ops_M(o, x, r);
+    for (long i = 0; i < mf; ++i) r[i] = f[i] - r[i];
+  }
+  if (iters) *iters = it;
+  free(V); free(Z); free(H); free(cs); free(sn); free(gv); free(y); free(dg); free(r);
+  return status;
+}
+
 /* ---------------------------------------------------------------- GKB */
 
 typedef struct {
   double tol;         /* tau of the lower-bound rule; <= 0 runs to maxit */
   int delay;          /* d */
   int maxit;          /* maximum number of zeta values (K) */
-  double inner_tol;   /* relative residual of each inner Jacobi-PCG solve */
+  double inner_tol;   /* relative residual of each inner solve */
   int inner_maxit;
   int squared_rule;   /* 1: literal squared comparison xi^2 <= tau * sum */
   /* optional outputs */
@@ -409,166 +592,460 @@ typedef struct {
   int store_k;        /* number of V and Q columns to store */
   double *V;          /* [store_k][m_full] */
   double *Q;          /* [store_k][n_cells] */
+  int inner_krylov;   /* 0: Jacobi-PCG, 1: FGMRES with Jacobi on the right */
+  int restart;        /* FGMRES restart (<= 0: 30) */
 } og_gkb_opts;
 
-/* Solve [[W, A], [A^T, 0]] [w; p] = [g; r].  Returns OG_OK, OG_MAXIT or an
-   error; *K = number of zeta values computed, *est = last lower-bound ratio. */
-int og_gkb_solve(const og_grid *g, const double *mu, double eta, const double *gv,
-                 const double *rv, const og_gkb_opts *o, double *w, double *p,
-                 int *K_out, double *est_out, int *inner_total) {
-  long mf = og_m_full(g), nc = og_n_cells(g);
-  if (eta < 0.0 || o->delay < 0 || o->maxit < 1) return OG_EINVAL;
-  double ninv = eta > 0.0 ? eta : 1.0; /* N^-1 = ninv * I */
+/* working state of one GKB run: the newest bidiagonalization vectors and
+   coefficients (generalized Golub-Kahan relations A Q = M V B,
+   A^T V = N Q B^T with V^T M V = I, Q^T N Q = I, Section 2.1) and the
+   Craig-variant iterates built from them */
+typedef struct {
+  const og_ops *o;
+  const og_gkb_opts *opt;
+  double ninv;            /* N^-1 = ninv I: eta for eta > 0, else 1 */
+  double *v, *Mv, *s, *y; /* velocity: v_k, M v_k, inner solution, M s */
+  double *f;              /* inner right-hand side */
+  double *q, *t;          /* pressure: q_k, unnormalised next q */
+  double alpha, beta;     /* alpha_k, beta_k */
+  double *u, *d, *p;      /* Craig iterates: u_k, direction d_k, p_k */
+  double zeta;
+  int solves, inner_total;
+} gk_state;
+
+static int gk_inner(gk_state *S, const double *f, double *x) {
+  int its = 0, st;
+  const og_gkb_opts *o = S->opt;
+  if (o->inner_krylov == 1)
+    st = fgmres_ops(S->o, f, x, o->inner_tol, o->restart > 0 ? o->restart : 30, o->inner_maxit,
+                    &its);
+  else
+    st = pcg_ops(S->o, f, x, o->inner_tol, o->inner_maxit, &its);
+  S->inner_total += its;
+  if (o->inner_iters) o->inner_iters[S->solves] = its;
+  S->solves += 1;
+  return st;
+}
+
+/* v = s / ||s||_M and M v from the inner solution s (alpha = ||s||_M by an
+   explicit product with M) */
+static int gk_normalise_v(gk_state *S) {
+  long m = S->o->m;
+  ops_M(S->o, S->s, S->y);
+  S->alpha = sqrt(dot(m, S->s, S->y));
+  if (!isfinite(S->alpha) || S->alpha == 0.0) return OG_ENAN;
+  for (long i = 0; i < m; ++i) {
+    S->v[i] = S->s[i] / S->alpha;
+    S->Mv[i] = S->y[i] / S->alpha;
+  }
+  return OG_OK;
+}
+
+/* first column of the bidiagonalization from b = r - A^T w0:
+   beta_1 = ||b||_{N^-1}, q_1 = N^-1 b / beta_1, M s = A q_1, alpha_1, v_1 */
+static int gk_first(gk_state *S, const double *b, double beta1) {
+  long n = S->o->n;
+  S->beta = beta1;
+  for (long i = 0; i < n; ++i) S->q[i] = S->ninv * b[i] / beta1;
+  S->o->A(S->o, S->q, S->f);
+  int st = gk_inner(S, S->f, S->s);
+  if (st != OG_OK) return st;
+  return gk_normalise_v(S);
+}
+
+/* next column: from A^T V = N Q B^T, beta_{k+1} N q_{k+1} = A^T v_k -
+   alpha_k N q_k, i.e. t = N^-1 A^T v_k - alpha_k q_k, beta = ||t||_N; from
+   A Q = M V B, alpha_{k+1} M v_{k+1} = A q_{k+1} - beta_{k+1} M v_k, solved
+   with the inner solver.  *breakdown = 1 when beta is at rounding level
+   (the Krylov space is exhausted). */
+static int gk_next(gk_state *S, int *breakdown) {
+  long m = S->o->m, n = S->o->n;
+  S->o->AT(S->o, S->v, S->t);
+  for (long i = 0; i < n; ++i) S->t[i] = S->ninv * S->t[i] - S->alpha * S->q[i];
+  double beta = sqrt(dot(n, S->t, S->t) / S->ninv);
+  if (!isfinite(beta)) return OG_ENAN;
+  *breakdown = beta <= 1e-13 * S->alpha;
+  if (*breakdown) return OG_OK;
+  S->beta = beta;
+  for (long i = 0; i < n; ++i) S->q[i] = S->t[i] / beta;
+  S->o->A(S->o, S->q, S->f);
+  for (long i = 0; i < m; ++i) S->f[i] -= beta * S->Mv[i];
+  int st = gk_inner(S, S->f, S->s);
+  if (st != OG_OK) return st;
+  return gk_normalise_v(S);
+}
+
+/* Craig-variant update with the newest column: zeta_k = beta_1 / alpha_1
+   at the first step, then -(beta_k / alpha_k) zeta_{k-1};
+   d_k = (q_k - beta_k d_{k-1}) / alpha_k; u_k = u_{k-1} + zeta_k v_k,
+   p_k = p_{k-1} - zeta_k d_k */
+static void craig_update(gk_state *S, int first) {
+  long m = S->o->m, n = S->o->n;
+  S->zeta = first ? S->beta / S->alpha : -(S->beta / S->alpha) * S->zeta;
+  for (long i = 0; i < n; ++i) {
+    S->d[i] = first ? S->q[i] / S->alpha : (S->q[i] - S->beta * S->d[i]) / S->alpha;
+    S->p[i] = first ? -S->zeta * S->d[i] : S->p[i] - S->zeta * S->d[i];
+  }
+  for (long i = 0; i < m; ++i) S->u[i] = first ? S->zeta * S->v[i] : S->u[i] + S->zeta * S->v[i];
+}
+
+/* lower bound of the energy-norm error relative to the solution, from the
+   newest delay+1 zeta values (Section 2.2); returns -1 before K = d+1 */
+static double lower_bound_ratio(const double *zs, int K, int delay, double sum_all,
+                                double *window) {
+  if (K < delay + 1) return -1.0;
+  double win = 0.0;
+  for (int j = K - delay; j <= K; ++j) win += zs[j - 1] * zs[j - 1];
+  *window = win;
+  return sqrt(win / sum_all);
+}
+
+/* One GKB run for [[W, A], [A^T, 0]] [w; p] = [g; r] on an operator bundle:
+   the transformation to a zero first right-hand side (Section 2: with
+   ghat = g + gamma A N^-1 r, w0 = M^-1 ghat, u = w - w0 solves the system
+   with right-hand side [0; b], b = r - A^T w0), the bidiagonalization with
+   the Craig-variant iterates, and the delayed lower-bound stopping rule. */
+static int gkb_run_ops(const og_ops *o, const double *gv, const double *rv,
+                       const og_gkb_opts *opt, double *w, double *p, int *K_out,
+                       double *est_out, int *inner_total) {
+  long mf = o->m, nc = o->n;
+  if (o->eta < 0.0 || opt->delay < 0 || opt->maxit < 1) return OG_EINVAL;
+  gk_state S;
+  memset(&S, 0, sizeof(S));
+  S.o = o;
+  S.opt = opt;
+  S.ninv = o->eta > 0.0 ? o->eta : 1.0;
   double *ghat = calloc(mf, sizeof(double)), *w0 = calloc(mf, sizeof(double));
-  double *u = calloc(mf, sizeof(double)), *v = calloc(mf, sizeof(double));
-  double *Mv = calloc(mf, sizeof(double)), *s = calloc(mf, sizeof(double));
-  double *y = calloc(mf, sizeof(double)), *f = calloc(mf, sizeof(double));
-  double *b = calloc(nc, sizeof(double)), *q = calloc(nc, sizeof(double));
-  double *d = calloc(nc, sizeof(double)), *t = calloc(nc, sizeof(double));
-  double *mask = calloc(mf, sizeof(double));
-  int status = OG_OK, K = 0, its = 0, tot = 0, solve_idx = 0;
+  double *b = calloc(nc, sizeof(double)), *zs = calloc(opt->maxit + 1, sizeof(double));
+  S.v = calloc(mf, sizeof(double));
+  S.Mv = calloc(mf, sizeof(double));
+  S.s = calloc(mf, sizeof(double));
+  S.y = calloc(mf, sizeof(double));
+  S.f = calloc(mf, sizeof(double));
+  S.u = calloc(mf, sizeof(double));
+  S.q = calloc(nc, sizeof(double));
+  S.t = calloc(nc, sizeof(double));
+  S.d = calloc(nc, sizeof(double));
+  S.p = p;
+  int status = OG_OK, K = 0;
   double est = 1.0;
 
-  double *zs = calloc(o->maxit + 1, sizeof(double)); /* zeta_1 .. zeta_K */
-  /* unknown-face mask: the diagonal of W is positive exactly there */
-  og_diag_M(g, mu, 0.0, mask);
-  for (long i = 0; i < mf; ++i) mask[i] = mask[i] > 0.0 ? 1.0 : 0.0;
-
-  /* transformation: ghat = g + gamma A N^-1 r, w0 = M^-1 ghat, b = r - A^T w0 */
-  for (long i = 0; i < mf; ++i) ghat[i] = gv[i] * mask[i];
-  if (eta > 0.0) {
+  /* transformation */
+  for (long i = 0; i < mf; ++i) ghat[i] = gv[i] * o->mask_m[i];
+  if (o->eta > 0.0) {
     double *rr = malloc(sizeof(double) * nc), *Ar = malloc(sizeof(double) * mf);
-    for (long i = 0; i < nc; ++i) rr[i] = (i == g->pin) ? 0.0 : rv[i];
-    og_apply_A(g, rr, Ar);
-    for (long i = 0; i < mf; ++i) ghat[i] += eta * Ar[i];
+    for (long i = 0; i < nc; ++i) rr[i] = rv[i] * o->mask_n[i];
+    o->A(o, rr, Ar);
+    for (long i = 0; i < mf; ++i) ghat[i] += o->eta * Ar[i];
     free(rr);
     free(Ar);
   }
   if (!all_zero(mf, ghat)) {
-    int st = og_pcg(g, mu, eta, ghat, w0, o->inner_tol, o->inner_maxit, &its);
-    tot += its;
-    if (o->inner_iters) o->inner_iters[solve_idx] = its;
+    int st = gk_inner(&S, ghat, w0);
     if (st != OG_OK) { status = st; goto done; }
+  } else {
+    S.solves = 1;
   }
-  ++solve_idx;
-  og_apply_AT(g, w0, b);
-  for (long i = 0; i < nc; ++i) b[i] = ((i == g->pin) ? 0.0 : rv[i]) - b[i];
+  o->AT(o, w0, b);
+  for (long i = 0; i < nc; ++i) b[i] = rv[i] * o->mask_n[i] - b[i];
 
-  /* initialisation of Algorithm 1 */
-  double beta1 = sqrt(ninv * dot(nc, b, b));
+  double beta1 = sqrt(S.ninv * dot(nc, b, b));
   for (long i = 0; i < nc; ++i) p[i] = 0.0;
   if (beta1 == 0.0) {
     est = 0.0;
     goto finish;
   }
-  for (long i = 0; i < nc; ++i) q[i] = ninv * b[i] / beta1;
-  og_apply_A(g, q, f);
   {
-    int st = og_pcg(g, mu, eta, f, s, o->inner_tol, o->inner_maxit, &its);
-    tot += its;
-    if (o->inner_iters) o->inner_iters[solve_idx] = its;
-    ++solve_idx;
+    int st = gk_first(&S, b, beta1);
     if (st != OG_OK) { status = st; goto done; }
   }
-  og_apply_M(g, mu, eta, s, y);
-  double alpha = sqrt(dot(mf, s, y));
-  if (!isfinite(alpha) || alpha == 0.0) { status = OG_ENAN; goto done; }
-  for (long i = 0; i < mf; ++i) {
-    v[i] = s[i] / alpha;
-    Mv[i] = y[i] / alpha;
-  }
-  double zeta = beta1 / alpha;
-  for (long i = 0; i < nc; ++i) {
-    d[i] = q[i] / alpha;
-    p[i] = -zeta * d[i];
-  }
-  for (long i = 0; i < mf; ++i) u[i] = zeta * v[i];
-  K = 1;
-  double sum_all = zeta * zeta;
-  zs[0] = zeta;
-  if (o->zeta) o->zeta[0] = zeta;
-  if (o->alpha) o->alpha[0] = alpha;
-  if (o->beta) o->beta[0] = beta1;
-  if (o->est_hist) o->est_hist[0] = -1.0;
-  if (o->store_k > 0) {
-    memcpy(o->V, v, sizeof(double) * mf);
-    memcpy(o->Q, q, sizeof(double) * nc);
-  }
-
   int converged = 0;
-  while (!converged && K < o->maxit) {
-    /* t = N^-1 (A^T v_k - alpha_k N q_k), beta = ||t||_N */
-    og_apply_AT(g, v, t);
-    for (long i = 0; i < nc; ++i) t[i] = ninv * t[i] - alpha * q[i];
-    double beta = sqrt(dot(nc, t, t) / ninv);
-    if (!isfinite(beta)) { status = OG_ENAN; goto done; }
-    if (beta <= 1e-13 * alpha) { /* breakdown: the Krylov space is exhausted */
+  double sum_all = 0.0;
+  for (;;) {
+    craig_update(&S, K == 0);
+    zs[K] = S.zeta;
+    if (opt->zeta) opt->zeta[K] = S.zeta;
+    if (opt->alpha) opt->alpha[K] = S.alpha;
+    if (opt->beta) opt->beta[K] = S.beta;
+    if (K < opt->store_k) {
+      memcpy(opt->V + (long)K * mf, S.v, sizeof(double) * mf);
+      memcpy(opt->Q + (long)K * nc, S.q, sizeof(double) * nc);
+    }
+    K += 1;
+    sum_all += S.zeta * S.zeta;
+    double win = 0.0;
+    double e = lower_bound_ratio(zs, K, opt->delay, sum_all, &win);
+    if (opt->est_hist) opt->est_hist[K - 1] = e;
+    if (e >= 0.0) {
+      est = e;
+      if (opt->tol > 0.0 && (opt->squared_rule ? (win <= opt->tol * sum_all) : (e <= opt->tol))) {
+        converged = 1;
+        break;
+      }
+    }
+    if (K >= opt->maxit) break;
+    int breakdown = 0;
+    int st = gk_next(&S, &breakdown);
+    if (st != OG_OK) { status = st; goto done; }
+    if (breakdown) {
       est = 0.0;
       converged = 1;
       break;
-    }
-    for (long i = 0; i < nc; ++i) q[i] = t[i] / beta;
-    /* s = M^-1 (A q - beta M v_k), alpha = ||s||_M */
-    og_apply_A(g, q, f);
-    for (long i = 0; i < mf; ++i) f[i] -= beta * Mv[i];
-    {
-      int st = og_pcg(g, mu, eta, f, s, o->inner_tol, o->inner_maxit, &its);
-      tot += its;
-      if (o->inner_iters) o->inner_iters[solve_idx] = its;
-      ++solve_idx;
-      if (st != OG_OK) { status = st; goto done; }
-    }
-    og_apply_M(g, mu, eta, s, y);
-    alpha = sqrt(dot(mf, s, y));
-    if (!isfinite(alpha) || alpha == 0.0) { status = OG_ENAN; goto done; }
-    for (long i = 0; i < mf; ++i) {
-      v[i] = s[i] / alpha;
-      Mv[i] = y[i] / alpha;
-    }
-    zeta = -(beta / alpha) * zeta;
-    for (long i = 0; i < nc; ++i) {
-      d[i] = (q[i] - beta * d[i]) / alpha;
-      p[i] -= zeta * d[i];
-    }
-    for (long i = 0; i < mf; ++i) u[i] += zeta * v[i];
-    zs[K] = zeta;
-    if (o->zeta) o->zeta[K] = zeta;
-    if (o->alpha) o->alpha[K] = alpha;
-    if (o->beta) o->beta[K] = beta;
-    if (K < o->store_k) {
-      memcpy(o->V + (long)K * mf, v, sizeof(double) * mf);
-      memcpy(o->Q + (long)K * nc, q, sizeof(double) * nc);
-    }
-    K += 1;
-    sum_all += zeta * zeta;
-    /* lower bound over the newest d+1 values zeta_{K-d} .. zeta_K */
-    if (K >= o->delay + 1) {
-      double win = 0.0;
-      for (int j = K - o->delay; j <= K; ++j) {
-        win += zs[j - 1] * zs[j - 1];
-      }
-      est = sqrt(win / sum_all);
-      if (o->est_hist) o->est_hist[K - 1] = est;
-      if (o->tol > 0.0) {
-        if (o->squared_rule ? (win <= o->tol * sum_all) : (est <= o->tol)) converged = 1;
-      }
-    } else if (o->est_hist) {
-      o->est_hist[K - 1] = -1.0;
     }
   }
   if (!converged) status = OG_MAXIT;
 
 finish:
-  for (long i = 0; i < mf; ++i) w[i] = (u[i] + w0[i]) * mask[i];
-  for (long i = 0; i < nc; ++i)
-    if (i == g->pin) p[i] = 0.0;
+  for (long i = 0; i < mf; ++i) w[i] = (S.u[i] + w0[i]) * o->mask_m[i];
+  for (long i = 0; i < nc; ++i) p[i] *= o->mask_n[i];
 done:
   if (K_out) *K_out = K;
   if (est_out) *est_out = est;
-  if (inner_total) *inner_total = tot;
-  free(ghat); free(w0); free(u); free(v); free(Mv); free(s); free(y); free(f);
-  free(b); free(q); free(d); free(t); free(mask); free(zs);
+  if (inner_total) *inner_total = S.inner_total;
+  free(ghat); free(w0); free(b); free(zs);
+  free(S.v); free(S.Mv); free(S.s); free(S.y); free(S.f); free(S.u);
+  free(S.q); free(S.t); free(S.d);
   return status;
+}
+
+/* Solve [[W, A], [A^T, 0]] [w; p] = [g; r] on the MAC grid.  Returns OG_OK,
+   OG_MAXIT or an error; *K = number of zeta values computed, *est = last
+   lower-bound ratio. */
+int og_gkb_solve(const og_grid *g, const double *mu, double eta, const double *gv,
+                 const double *rv, const og_gkb_opts *o, double *w, double *p,
+                 int *K_out, double *est_out, int *inner_total) {
+  og_ops ops;
+  mac_data md;
+  if (eta < 0.0 || o->delay < 0 || o->maxit < 1) return OG_EINVAL;
+  if (mac_ops(&ops, &md, g, mu, eta) != OG_OK) return OG_ENOMEM;
+  int st = gkb_run_ops(&ops, gv, rv, o, w, p, K_out, est_out, inner_total);
+  mac_ops_free(&ops);
+  return st;
+}
+
+/* ------------------------------------------- GKB as a preconditioner */
+
+/* y = K x for the saddle matrix K = [[W, A], [A^T, 0]] on the unknowns;
+   x, y: velocity block then pressure block */
+static void saddle_apply(const og_ops *o, const double *x, double *y) {
+  long m = o->m, n = o->n;
+  double *Ap = malloc(sizeof(double) * m);
+  double *xp = malloc(sizeof(double) * n);
+  for (long i = 0; i < n; ++i) xp[i] = x[m + i] * o->mask_n[i];
+  o->W(o, x, y);
+  o->A(o, xp, Ap);
+  for (long i = 0; i < m; ++i) y[i] = (y[i] + Ap[i]) * o->mask_m[i];
+  o->AT(o, x, y + m);
+  for (long i = 0; i < n; ++i) y[m + i] *= o->mask_n[i];
+  free(Ap);
+  free(xp);
+}
+
+/* Flexible GMRES (restart `restart`, modified Gram-Schmidt, Givens
+   rotations) on the whole saddle system, right preconditioned by one GKB run
+   per step (the GKB options of `gopt`); Section 3 offers GKB as a solver or
+   as a preconditioner.  Stops when the residual norm of the least-squares
+   problem, or the true residual at a restart, is <= tol ||[g; r]||, or after
+   maxit steps (OG_MAXIT).  *iters: outer steps (= GKB runs). */
+static int gkb_fgmres_ops(const og_ops *o, const double *gv, const double *rv,
+                          const og_gkb_opts *gopt, double tol, int restart, int maxit,
+                          double *w, double *p, int *iters, int *inner_total) {
+  long m = o->m, n = o->n, N = m + n;
+  int R = restart;
+  double *V = malloc(sizeof(double) * N * (R + 1)), *Z = malloc(sizeof(double) * N * R);
+  double *H = calloc((size_t)(R + 1) * R, sizeof(double));
+  double *cs = malloc(sizeof(double) * R), *sn = malloc(sizeof(double) * R);
+  double *gr = malloc(sizeof(double) * (R + 1)), *y = malloc(sizeof(double) * R);
+  double *bb = malloc(sizeof(double) * N), *x = calloc(N, sizeof(double));
+  double *r = malloc(sizeof(double) * N);
+  for (long i = 0; i < m; ++i) bb[i] = gv[i] * o->mask_m[i];
+  for (long i = 0; i < n; ++i) bb[m + i] = rv[i] * o->mask_n[i];
+  memcpy(r, bb, sizeof(double) * N);
+  double bnorm2 = dot(N, bb, bb);
+  int it = 0, status = OG_MAXIT, tot = 0;
+  for (;;) {
+    double beta = sqrt(dot(N, r, r));
+    if (!isfinite(beta)) { status = OG_ENAN; break; }
+    if (beta * beta <= tol * tol * bnorm2) { status = OG_OK; break; }
+    if (it >= maxit) break;
+    for (long i = 0; i < N; ++i) V[i] = r[i] / beta;
+    for (int i = 0; i <= R; ++i) gr[i] = 0.0;
+    gr[0] = beta;
+    int k = 0, conv = 0, err = OG_OK;
+    for (int j = 0; j < R && it < maxit; ++j) {
+      double *vj = V + (long)j * N, *zj = Z + (long)j * N, *wv = V + (long)(j + 1) * N;
+      int K = 0, its = 0;
+      double est = 0.0;
+      int st = gkb_run_ops(o, vj, vj + m, gopt, zj, zj + m, &K, &est, &its);
+      tot += its;
+      if (st < 0) { err = st; break; }
+      saddle_apply(o, zj, wv);
+      for (int i = 0; i <= j; ++i) {
+        double hij = dot(N, wv, V + (long)i * N);
+        H[(long)i * R + j] = hij;
+        for (long l = 0; l < N; ++l) wv[l] -= hij * V[(long)i * N + l];
+      }
+      double hn = sqrt(dot(N, wv, wv));
+      for (int i = 0; i < j; ++i) {
+        double a = H[(long)i * R + j], b = H[(long)(i + 1) * R + j];
+        H[(long)i * R + j] = cs[i] * a + sn[i] * b;
+        H[(long)(i + 1) * R + j] = -sn[i] * a + cs[i] * b;
+      }
+      double a = H[(long)j * R + j], rr = sqrt(a * a + hn * hn);
+      ++it;
+      if (rr == 0.0) break;
+      cs[j] = a / rr;
+      sn[j] = hn / rr;
+      H[(long)j * R + j] = rr;
+      gr[j + 1] = -sn[j] * gr[j];
+      gr[j] = cs[j] * gr[j];
+      k = j + 1;
+      if (gr[j + 1] * gr[j + 1] <= tol * tol * bnorm2 || hn == 0.0) { conv = 1; break; }
+      for (long l = 0; l < N; ++l) wv[l] /= hn;
+    }
+    if (err != OG_OK) { status = err; break; }
+    for (int i = k - 1; i >= 0; --i) {
+      double v = gr[i];
+      for (int l = i + 1; l < k; ++l) v -= H[(long)i * R + l] * y[l];
+      y[i] = v / H[(long)i * R + i];
+    }
+    for (int l = 0; l < k; ++l)
+      for (long i = 0; i < N; ++i) x[i] += y[l] * Z[(long)l * N + i];
+    if (conv) { status = OG_OK; break; }
+    saddle_apply(o, x, r);
+    for (long i = 0; i < N; ++i) r[i] = bb[i] - r[i];
+  }
+  for (long i = 0; i < m; ++i) w[i] = x[i] * o->mask_m[i];
+  for (long i = 0; i < n; ++i) p[i] = x[m + i] * o->mask_n[i];
+  if (iters) *iters = it;
+  if (inner_total) *inner_total = tot;
+  free(V); free(Z); free(H); free(cs); free(sn); free(gr); free(y); free(bb); free(x); free(r);
+  return status;
+}
+
+int og_gkb_fgmres(const og_grid *g, const double *mu, double eta, const double *gv,
+                  const double *rv, const og_gkb_opts *o, double tol, int restart, int maxit,
+                  double *w, double *p, int *iters, int *inner_total) {
+  og_ops ops;
+  mac_data md;
+  if (eta < 0.0 || restart < 1 || maxit < 1 || !(tol > 0.0)) return OG_EINVAL;
+  if (mac_ops(&ops, &md, g, mu, eta) != OG_OK) return OG_ENOMEM;
+  int st = gkb_fgmres_ops(&ops, gv, rv, o, tol, restart, maxit, w, p, iters, inner_total);
+  mac_ops_free(&ops);
+  return st;
+}
+
+/* --------------------------------------------------- assembled (CSR) system */
+
+/* a saddle system given by CSR blocks W (m x m) and A (m x n) */
+typedef struct {
+  const int *wp, *wc;
+  const double *wv;
+  const int *ap, *ac;
+  const double *av;
+} csr_data;
+
+static void csr_W(const og_ops *o, const double *x, double *y) {
+  const csr_data *d = o->data;
+  for (long i = 0; i < o->m; ++i) {
+    double acc = 0.0;
+    for (int e = d->wp[i]; e < d->wp[i + 1]; ++e) acc += d->wv[e] * x[d->wc[e]];
+    y[i] = acc;
+  }
+}
+static void csr_A(const og_ops *o, const double *p, double *y) {
+  const csr_data *d = o->data;
+  for (long i = 0; i < o->m; ++i) {
+    double acc = 0.0;
+    for (int e = d->ap[i]; e < d->ap[i + 1]; ++e) acc += d->av[e] * p[d->ac[e]];
+    y[i] = acc;
+  }
+}
+static void csr_AT(const og_ops *o, const double *x, double *t) {
+  const csr_data *d = o->data;
+  for (long k = 0; k < o->n; ++k) t[k] = 0.0;
+  for (long i = 0; i < o->m; ++i)
+    for (int e = d->ap[i]; e < d->ap[i + 1]; ++e) t[d->ac[e]] += d->av[e] * x[i];
+}
+static void csr_diag(const og_ops *o, double *dg) {
+  const csr_data *d = o->data;
+  for (long i = 0; i < o->m; ++i) {
+    double w = 0.0, a = 0.0;
+    for (int e = d->wp[i]; e < d->wp[i + 1]; ++e)
+      if (d->wc[e] == i) w += d->wv[e];
+    for (int e = d->ap[i]; e < d->ap[i + 1]; ++e) a += d->av[e] * d->av[e];
+    dg[i] = w + o->eta * a;
+  }
+}
+
+/* central scaling of Section 4.1: sw = diag(W)^-1/2 (m), sp = diag(A^T
+   diag(W)^-1 A)^-1/2 (n).  Returns OG_EINVAL for a non-positive diagonal
+   entry of W or an empty column of A. */
+int og_csr_central_scaling(int m, int n, const int *wp, const int *wc, const double *wv,
+                           const int *ap, const int *ac, const double *av, double *sw,
+                           double *sp) {
+  for (int i = 0; i < m; ++i) {
+    double dw = 0.0;
+    for (int e = wp[i]; e < wp[i + 1]; ++e)
+      if (wc[e] == i) dw += wv[e];
+    if (!(dw > 0.0)) return OG_EINVAL;
+    sw[i] = dw; /* D for now */
+  }
+  for (int k = 0; k < n; ++k) sp[k] = 0.0;
+  for (int i = 0; i < m; ++i)
+    for (int e = ap[i]; e < ap[i + 1]; ++e) sp[ac[e]] += av[e] * av[e] / sw[i];
+  for (int k = 0; k < n; ++k) {
+    if (!(sp[k] > 0.0)) return OG_EINVAL;
+    sp[k] = 1.0 / sqrt(sp[k]);
+  }
+  for (int i = 0; i < m; ++i) sw[i] = 1.0 / sqrt(sw[i]);
+  return OG_OK;
+}
+
+/* GKB on an assembled system, optionally centrally scaled: the scaled
+   blocks S_w W S_w and S_w A S_p are formed explicitly, GKB solves the
+   scaled system for the right-hand sides S_w g, S_p r, and the solution is
+   scaled back, w = S_w w', p = S_p p' (the scaling changes the iterates, not
+   the solution of the system). */
+int og_gkb_solve_csr(int m, int n, const int *wp, const int *wc, const double *wv,
+                     const int *ap, const int *ac, const double *av, double eta, int scaling,
+                     const double *gv, const double *rv, const og_gkb_opts *opt, double *w,
+                     double *p, int *K_out, double *est_out, int *inner_total) {
+  if (m < 1 || n < 1 || eta < 0.0 || opt->delay < 0 || opt->maxit < 1) return OG_EINVAL;
+  long nw = wp[m], na = ap[m];
+  double *sw = malloc(sizeof(double) * m), *sp = malloc(sizeof(double) * n);
+  double *wsc = malloc(sizeof(double) * (nw > 0 ? nw : 1));
+  double *asc = malloc(sizeof(double) * (na > 0 ? na : 1));
+  double *gs = malloc(sizeof(double) * m), *rs = malloc(sizeof(double) * n);
+  double *mm = malloc(sizeof(double) * m), *mn = malloc(sizeof(double) * n);
+  int st = OG_OK;
+  if (scaling) {
+    st = og_csr_central_scaling(m, n, wp, wc, wv, ap, ac, av, sw, sp);
+  } else {
+    for (int i = 0; i < m; ++i) sw[i] = 1.0;
+    for (int k = 0; k < n; ++k) sp[k] = 1.0;
+  }
+  if (st == OG_OK) {
+    for (int i = 0; i < m; ++i)
+      for (int e = wp[i]; e < wp[i + 1]; ++e) wsc[e] = sw[i] * wv[e] * sw[wc[e]];
+    for (int i = 0; i < m; ++i)
+      for (int e = ap[i]; e < ap[i + 1]; ++e) asc[e] = sw[i] * av[e] * sp[ac[e]];
+    for (int i = 0; i < m; ++i) {
+      gs[i] = sw[i] * gv[i];
+      mm[i] = 1.0;
+    }
+    for (int k = 0; k < n; ++k) {
+      rs[k] = sp[k] * rv[k];
+      mn[k] = 1.0;
+    }
+    csr_data d = {wp, wc, wsc, ap, ac, asc};
+    og_ops o = {m, n, eta, &d, csr_W, csr_A, csr_AT, csr_diag, mm, mn};
+    st = gkb_run_ops(&o, gs, rs, opt, w, p, K_out, est_out, inner_total);
+    for (int i = 0; i < m; ++i) w[i] *= sw[i];
+    for (int k = 0; k < n; ++k) p[k] *= sp[k];
+  }
+  free(sw); free(sp); free(wsc); free(asc); free(gs); free(rs); free(mm); free(mn);
+  return st;
 }
 
 /* ---------------------------------------------------------- saddle residual */

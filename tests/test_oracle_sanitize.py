@@ -18,6 +18,7 @@ typedef struct { int dim; int n[3]; double h; int bc[6]; int pin; } og_grid;
 typedef struct {
   double tol; int delay; int maxit; double inner_tol; int inner_maxit; int squared_rule;
   double *zeta, *alpha, *beta, *est_hist; int *inner_iters; int store_k; double *V, *Q;
+  int inner_krylov; int restart;
 } og_gkb_opts;
 long og_m_full(const og_grid *g);
 long og_n_cells(const og_grid *g);
@@ -27,6 +28,9 @@ int og_gkb_solve(const og_grid *g, const double *mu, double eta, const double *g
 void og_saddle_residual(const og_grid *g, const double *mu, const double *gv,
                         const double *rv, const double *w, const double *p,
                         double *res_w, double *res_r, double *norms);
+int og_gkb_fgmres(const og_grid *g, const double *mu, double eta, const double *gv,
+                  const double *rv, const og_gkb_opts *o, double tol, int restart, int maxit,
+                  double *w, double *p, int *iters, int *inner_total);
 
 static int run(og_grid g, int varmu, double eta) {
   long mf = og_m_full(&g), nc = og_n_cells(&g);
@@ -43,9 +47,24 @@ static int run(og_grid g, int varmu, double eta) {
   int st = og_gkb_solve(&g, mu, eta, gv, rv, &o, w, p, &K, &e, &tot);
   double *resw = malloc(mf * sizeof(double)), *resr = malloc(nc * sizeof(double));
   og_saddle_residual(&g, mu, gv, rv, w, p, resw, resr, norms);
-  free(resw); free(resr);
   printf("dim %d status %d K %d inner %d residual %.3e\n", g.dim, st, K, tot, norms[0] / norms[3]);
   int ok = st == 0 && norms[0] <= 1e-7 * norms[3];
+  /* FGMRES inner solves (restart 7) and GKB as the preconditioner of an
+     outer FGMRES (restart 3) on the same system */
+  o.inner_krylov = 1;
+  o.restart = 7;
+  st = og_gkb_solve(&g, mu, eta, gv, rv, &o, w, p, &K, &e, &tot);
+  og_saddle_residual(&g, mu, gv, rv, w, p, resw, resr, norms);
+  ok = ok && st == 0 && norms[0] <= 1e-7 * norms[3];
+  o.tol = 1e-2;
+  o.delay = 2;
+  int its = 0;
+  st = og_gkb_fgmres(&g, mu, eta, gv, rv, &o, 1e-9, 3, 40, w, p, &its, &tot);
+  og_saddle_residual(&g, mu, gv, rv, w, p, resw, resr, norms);
+  printf("  fgmres inner / gkb-preconditioned fgmres: status %d its %d residual %.3e\n", st, its,
+         norms[0] / norms[3]);
+  ok = ok && st == 0 && norms[0] <= 1e-8 * norms[3];
+  free(resw); free(resr);
   free(gv); free(w); free(rv); free(p); free(mu); free(zeta); free(est); free(inner);
   return ok ? 0 : 1;
 }
@@ -86,4 +105,4 @@ def test_oracle_under_address_and_ub_sanitizers(tmp_path):
         env["ASAN_OPTIONS"] = "detect_leaks=0"
         r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
     assert r.returncode == 0, r.stdout + r.stderr[-4000:]
-    assert r.stdout.count("status 0") == 3
+    assert r.stdout.count("status 0") == 6  # three GKB solves, three FGMRES runs
