@@ -14,12 +14,23 @@ same problem timed:
   fp64_gkb1        FP64, one GKB run to the target (no defect correction)
   *_mg_hybrid      FP64 / FP32 inner MG-PCG with the face + edge smoother
 
-`value` is the time of --mode (default mixed_learned); the others are in
-config.compare_seconds.  The CNN of the learned mode is trained first on
-pairs captured from MG-PCG inner solves of a different forcing (seed 1000);
-capture and training time are reported apart from the solve time.
+  mixed_mg_fgmres  FP32 inner FGMRES(30) with the V-cycle on the right
+  fp64_gkb_precond FGMRES on the saddle system, right preconditioned by one
+                   loose GKB run per step (GKB as a preconditioner)
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--mode mixed_learned]
+`value` is the mean time of --mode (default mixed_learned) over the K timed
+steps; step i solves forcing seed seeds[i % len(seeds)] (default 0, 1, 2),
+every right-hand side resident in HBM before the timed region.  Each solve
+is bracketed by HIP events on the caller's stream (gkb_solve returns when its
+work is done); config.details has the per-seed median and minimum.  The other
+modes are timed on one solve per seed after one warm-up solve
+(config.compare_seconds).  The CNN of the learned mode is trained first on
+pairs captured from MG-PCG inner solves of a different forcing (seed 1000);
+capture and training time are reported apart from the solve time, and
+config.learned says whether the network carried the inner solves.
+
+    python bench.py [--gpus 1] [--steps 6] [--warmup 1] [--mode mixed_learned]
+    python bench.py --study eta      # K and inner iterations against eta
 """
 from __future__ import annotations
 
@@ -52,6 +63,15 @@ MODES = {
     "fp64_gkb1": ("fp64", "mg", 1e-9, 1e-10, 5, "jacobi", 2),
     "fp64_mg_hybrid": ("fp64", "mg", 3e-3, 3e-4, 2, "hybrid", 1),
     "mixed_mg_hybrid": ("mixed", "mg", 3e-3, 3e-4, 2, "hybrid", 1),
+    # FGMRES(30) inner solves with the same V-cycle and settings as mixed_mg
+    "mixed_mg_fgmres": ("mixed", "mg", 1e-2, 3e-4, 2, "jacobi", 2),
+    # outer FGMRES(10) on the saddle system, one GKB run (tau = 1e-2, d = 2,
+    # FP64 MG-PCG inner solves at 1e-3) per step as the right preconditioner
+    "fp64_gkb_precond": ("fp64", "mg", 1e-2, 1e-3, 2, "jacobi", 2),
+}
+EXTRA = {
+    "mixed_mg_fgmres": dict(krylov="fgmres", fgmres_restart=30),
+    "fp64_gkb_precond": dict(method="precond", outer_restart=10),
 }
 CNN_CHANNELS = (4, 8, 8, 3)  # 3 conv3x3x3 layers, 8 hidden channels
 
@@ -109,6 +129,7 @@ def make_solver(gk, pr, mode, net=None):
     kw = dict(precision=prec, inner=inner, nu_pre=nu, nu_post=nu, inner_tol=itol,
               smoother=smoother, inner_maxit=5000, maxit=200, refine_tol=1e-8, max_sweeps=12,
               check_every=8)
+    kw.update(EXTRA.get(mode, {}))
     s = gk.Solver(pr.grid, pr.mu, pr.eta, **kw)
     if inner == "learned":
         s.attach_cnn(net)
@@ -146,80 +167,172 @@ def train_cnn(gk, torch, problems, n, weights=None):
                  "loss_last": round(float(losses[-1]), 5)}
 
 
-def time_mode(gk, torch, pr, mode, steps, warmup, g, r, net=None):
+def _median(v):
+    v = sorted(v)
+    n = len(v)
+    return v[n // 2] if n % 2 else 0.5 * (v[n // 2 - 1] + v[n // 2])
+
+
+def timed_solve(torch, s, g, r, tol, delay):
+    """One gkb_solve bracketed by HIP events on the caller's stream (the
+    library waits for that stream on entry and returns when its own work is
+    complete); returns (seconds, w, p, info)."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    w, p, info = s.solve(g, r, tol=tol, delay=delay)
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e-3, w, p, info
+
+
+def time_mode(gk, torch, prs, rhs, mode, steps, warmup, net=None):
+    """Set up the solver of `mode` on the first problem, run `warmup` untimed
+    solves, then `steps` timed solves cycling over the right-hand sides.
+    Returns the solver and a record with the mean, per-seed median / minimum
+    and the statistics of every solve."""
     t0 = time.perf_counter()
-    s = make_solver(gk, pr, mode, net)
+    s = make_solver(gk, prs[0], mode, net)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     tol, delay = MODES[mode][2], MODES[mode][4]
-    info = None
-    for _ in range(warmup):
-        w, p, info = s.solve(g, r, tol=tol, delay=delay)
+    for i in range(warmup):
+        g, r = rhs[i % len(rhs)]
+        s.solve(g, r, tol=tol, delay=delay)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        w, p, info = s.solve(g, r, tol=tol, delay=delay)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    norms, _, _ = s.residual(g, r, w, p)
-    rel = norms[0] / norms[3]
-    return s, w, p, dict(seconds=dt, setup_s=setup_s, residual=rel, sweeps=info["sweeps"],
-                         outer_iterations=info["outer_iterations"],
-                         inner_iterations=info["inner_iterations"],
-                         inner_solves=info["inner_solves"], fallbacks=info["fallbacks"],
-                         mg_levels=info["mg_levels"])
+    per_seed = {}
+    total = 0.0
+    learned = dict(learned_solves=0, fallbacks=0, inner_solves=0, gain=[], reasons=[])
+    for i in range(steps):
+        k = i % len(rhs)
+        g, r = rhs[k]
+        dt, w, p, info = timed_solve(torch, s, g, r, tol, delay)
+        total += dt
+        norms, _, _ = s.residual(g, r, w, p)
+        d = per_seed.setdefault(prs[k].extra["seed"], dict(times=[], residual=0.0, sweeps=[],
+                                                           outer=[], inner=[]))
+        d["times"].append(dt)
+        d["residual"] = max(d["residual"], norms[0] / norms[3])
+        d["sweeps"].append(info["sweeps"])
+        d["outer"].append(info["outer_iterations"])
+        d["inner"].append(info["inner_iterations"])
+        for key in ("learned_solves", "fallbacks", "inner_solves"):
+            learned[key] += info[key]
+        learned["gain"].append(round(info["learned_gain"], 5))
+        learned["reasons"].append(info["learned_fallback_reason"])
+    rec = dict(seconds=total / steps, setup_s=round(setup_s, 3), mg_levels=s.stats()["mg_levels"],
+               per_seed={str(k): dict(median_s=round(_median(v["times"]), 5),
+                                      min_s=round(min(v["times"]), 5), n=len(v["times"]),
+                                      residual=v["residual"], sweeps=v["sweeps"][-1],
+                                      outer_iterations=v["outer"][-1],
+                                      inner_iterations=v["inner"][-1])
+                         for k, v in per_seed.items()})
+    if MODES[mode][1] == "learned":
+        rec["learned"] = dict(
+            network_used=learned["learned_solves"] > learned["fallbacks"],
+            learned_solves=learned["learned_solves"], fallbacks=learned["fallbacks"],
+            inner_solves=learned["inner_solves"], gain=learned["gain"][-1],
+            fallback_reason=learned["reasons"][-1])
+    return s, rec
 
 
-def cpu_baseline(pr):
-    """The CPU FP64 oracle (GKB + Jacobi-PCG) on a bounded sample: 20
-    Jacobi-PCG iterations on the full problem (seconds per iteration), and
-    complete oracle solves of the same problem family at 8^3 and 16^3 (inner
-    iteration counts); the count is projected to the full grid with the
-    growth exponent measured between those two sizes."""
-    import math
+# the oracle's method on the benchmarked workload: one FP64 GKB run whose
+# lower-bound tolerance alone reaches the 1e-8 residual, Jacobi-PCG inner
+# solves (the oracle's inner solver)
+ORACLE_METHOD = dict(tol=1e-9, delay=5, inner_tol=1e-10)
 
+
+def cpu_baseline(gk, torch, pr, g, r, sample_iters=200):
+    """The CPU FP64 oracle on a bounded sample of the benchmarked workload:
+    `sample_iters` Jacobi-PCG iterations of its GKB solve on the full grid
+    are timed (seconds per inner iteration, every host thread), and the
+    number of inner iterations its complete solve takes is counted by running
+    the identical method (FP64 GKB, Jacobi-PCG inner solves, the same
+    tolerances; parity-tested against the oracle) through the library.  The
+    oracle's time for the whole solve is their product."""
     import oracle
-    import problems
 
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     oracle.lib()
     t0 = time.perf_counter()
-    oracle.gkb_solve(pr.grid, pr.g, pr.r, pr.eta, mu=pr.mu, tol=1e-9, delay=5, maxit=1,
-                     inner_tol=1e-10, inner_maxit=20)
-    t_iter = (time.perf_counter() - t0) / 20.0
-    its, t_small = {}, {}
-    for n in (8, 16):
-        sp = problems.stokes_problem(3, n, seed=0, eta=pr.eta, lid=True)
-        t1 = time.perf_counter()
-        rs = oracle.gkb_solve(sp.grid, sp.g, sp.r, sp.eta, tol=1e-9, delay=5, maxit=200,
-                              inner_tol=1e-10, inner_maxit=10 ** 7)
-        t_small[n] = time.perf_counter() - t1
-        its[n] = rs["inner_total"]
-    expo = math.log(its[16] / its[8]) / math.log(2.0)
-    n_big = pr.grid.n[0]
-    its_big = its[16] * (n_big / 16.0) ** expo
-    return {"value": round(t_iter * its_big, 1), "unit": "s", "cores": threads, "kind": "oracle",
-            "sample": (f"projection: oracle FP64 GKB + Jacobi-PCG took {t_iter:.3f} s per inner "
-                       f"iteration over 20 iterations at {n_big}^3; full oracle solves at 8^3 / "
-                       f"16^3 needed {its[8]} / {its[16]} inner iterations "
-                       f"({t_small[8]:.1f} s / {t_small[16]:.1f} s), growth n^{expo:.2f}, "
-                       f"projected {its_big:.3g} iterations at {n_big}^3")}
+    oracle.gkb_solve(pr.grid, pr.g, pr.r, pr.eta, mu=pr.mu, tol=ORACLE_METHOD["tol"],
+                     delay=ORACLE_METHOD["delay"], maxit=1, inner_tol=ORACLE_METHOD["inner_tol"],
+                     inner_maxit=sample_iters)
+    t_iter = (time.perf_counter() - t0) / sample_iters
+    # the same method on the GPU, counted (not timed)
+    s = gk.Solver(pr.grid, pr.mu, pr.eta, precision="fp64", inner="jacobi",
+                  inner_tol=ORACLE_METHOD["inner_tol"], inner_maxit=10 ** 7, maxit=400,
+                  check_every=64)
+    t1 = time.perf_counter()
+    w, p, info = s.solve(g, r, tol=ORACLE_METHOD["tol"], delay=ORACLE_METHOD["delay"])
+    gpu_s = time.perf_counter() - t1
+    norms, _, _ = s.residual(g, r, w, p)
+    s.close()
+    its = info["inner_iterations"]
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": round(t_iter * its, 1), "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": (f"oracle FP64 GKB with Jacobi-PCG inner solves (tau 1e-9, d 5, tau_in "
+                       f"1e-10) on the full {pr.grid.n[0]}^3 workload: {sample_iters} inner "
+                       f"iterations timed, {t_iter:.4f} s each on {threads} threads ({model}); "
+                       f"the complete solve takes {its} inner iterations in {info['outer_iterations']}"
+                       f" GKB steps (counted by the same method in the library, {gpu_s:.1f} s on "
+                       f"the GPU, FP64 residual {norms[0] / norms[3]:.1e}); value = their product"),
+            "inner_iterations": its, "seconds_per_iteration": t_iter,
+            "gpu_same_method_s": round(gpu_s, 3)}
+
+
+def study_eta(gk, torch, problems):
+    """K, inner iterations and time against eta on the 2D 512^2 and 3D 128^3
+    workloads, mixed precision, both smoothers (one JSON line per case)."""
+    rows = []
+    for dim, n, lid in ((2, 512, False), (3, 128, True)):
+        for smoother, nu, tol, itol in (("jacobi", 2, 1e-2, 3e-4), ("hybrid", 1, 3e-3, 3e-4)):
+            for eta in (0.0, 1.0, 10.0, 1e2, 1e3):
+                pr = problems.stokes_problem(dim, n, seed=0, eta=eta, lid=lid)
+                g = torch.tensor(pr.g, device="cuda")
+                r = torch.tensor(pr.r, device="cuda")
+                s = gk.Solver(pr.grid, None, eta, precision="mixed", inner="mg",
+                              smoother=smoother, nu_pre=nu, nu_post=nu, inner_tol=itol,
+                              inner_maxit=20000, maxit=3000, refine_tol=1e-8, max_sweeps=30)
+                s.solve(g, r, tol=tol, delay=2)  # warm-up (graph capture)
+                dt, w, p, info = timed_solve(torch, s, g, r, tol, 2)
+                norms, _, _ = s.residual(g, r, w, p)
+                s.close()
+                row = dict(workload=f"stokes{dim}d_{n}" + ("_lid" if lid else ""),
+                           smoother=smoother, eta=eta, seconds=round(dt, 4),
+                           outer_iterations=info["outer_iterations"], sweeps=info["sweeps"],
+                           inner_iterations=info["inner_iterations"],
+                           inner_per_solve=round(info["inner_iterations"] /
+                                                 max(info["inner_solves"], 1), 1),
+                           residual=norms[0] / norms[3])
+                rows.append(row)
+                print(json.dumps(row), flush=True)
+    return rows
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", default="mixed_learned", choices=list(MODES))
     ap.add_argument("--n", type=int, default=128, help="cells per axis of the 3D problem")
-    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--seeds", default="0,1,2", help="forcing seeds cycled over the steps")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--weights", default=None, help="CNN checkpoint for mixed_learned")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the calibration copy and 20 launches of the dominant kernel "
                          "(hardware-counter runs)")
+    ap.add_argument("--study", choices=["eta"], default=None)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this solver has no multi-GPU path "
@@ -232,10 +345,14 @@ def main():
     import paper_2001_10424_amd as gk
 
     torch.cuda.set_device(0)
-    pr = problems.stokes_problem(3, args.n, seed=args.seed, eta=1e3, lid=True)
-    g = torch.tensor(pr.g, device="cuda")
-    r = torch.tensor(pr.r, device="cuda")
-    log(f"[bench] workload stokes3d_{args.n}_lid m={pr.grid.m} n={pr.grid.n_p}")
+    if args.study == "eta":
+        study_eta(gk, torch, problems)
+        return
+    seeds = [int(x) for x in args.seeds.split(",")]
+    prs = [problems.stokes_problem(3, args.n, seed=sd, eta=1e3, lid=True) for sd in seeds]
+    rhs = [(torch.tensor(p.g, device="cuda"), torch.tensor(p.r, device="cuda")) for p in prs]
+    pr = prs[0]
+    log(f"[bench] workload stokes3d_{args.n}_lid m={pr.grid.m} n={pr.grid.n_p} seeds={seeds}")
 
     # calibration copy of known size for the HBM counters (256 MiB read +
     # 256 MiB written): one torch copy kernel in every profiled run
@@ -249,7 +366,7 @@ def main():
         # counter runs: the calibration copy above plus launches of the
         # dominant kernel on the buffers of one inner solve
         s = make_solver(gk, pr, "mixed_mg")
-        s.inner_solve(g, 1e-3)
+        s.inner_solve(rhs[0][0], 1e-3)
         ms = s.time_kernel("smooth_prolong", 20)
         print(json.dumps({"kernel_only": True, "smooth_prolong_avg_ms": ms, "m_full": s.m_full,
                           "m_full_coarse": coarse_faces(pr.grid)}))
@@ -261,14 +378,14 @@ def main():
         net, train_info = train_cnn(gk, torch, problems, args.n, args.weights)
         log(f"[bench] cnn {json.dumps(train_info)}")
 
-    s, w, p, main_res = time_mode(gk, torch, pr, args.mode, args.steps, args.warmup, g, r, net)
+    s, main_res = time_mode(gk, torch, prs, rhs, args.mode, args.steps, args.warmup, net)
     log(f"[bench] {args.mode}: {json.dumps(main_res)}")
     compare = {args.mode: main_res}
     if not args.no_compare:
         for m in MODES:
             if m == args.mode or (m == "mixed_learned" and net is None):
                 continue
-            s2, _, _, res2 = time_mode(gk, torch, pr, m, args.steps, args.warmup, g, r, net)
+            s2, res2 = time_mode(gk, torch, prs, rhs, m, len(rhs), 1, net)
             compare[m] = res2
             s2.close()
             log(f"[bench] {m}: {json.dumps(res2)}")
@@ -292,7 +409,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(pr)
+        cpu = cpu_baseline(gk, torch, pr, rhs[0][0], rhs[0][1])
         log(f"[bench] cpu_baseline {json.dumps(cpu)}")
 
     out = {
@@ -309,13 +426,16 @@ def main():
         "dtype": "f32+f64" if MODES[args.mode][0] == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": f"stokes3d_{args.n}_lid: 3D Stokes, MAC {args.n}^3, mu=1, "
-                               f"lid u=1 on +z, 8-mode Fourier body force (seed {args.seed}), "
-                               f"eta=1e3, stop at FP64 relative saddle residual 1e-8",
+                               f"lid u=1 on +z, 8-mode Fourier body force (seeds {args.seeds}, "
+                               f"cycled over the steps), eta=1e3, stop at FP64 relative saddle "
+                               f"residual 1e-8",
                    "mode": args.mode,
                    "inner": "PCG / flexible CG with geometric MG V(2,2), weighted Jacobi, "
                             "5 levels, FP64 dense coarsest solve (*_hybrid: V(1,1) with the "
                             "face + edge hybrid smoother)",
+                   "timing": "HIP events around each gkb_solve; value = mean of the timed steps",
                    "compare_seconds": {k: round(v["seconds"], 5) for k, v in compare.items()},
+                   "learned": main_res.get("learned"),
                    "details": compare,
                    "cnn_training": train_info},
         "roofline": roofline,

@@ -71,6 +71,25 @@ extern "C" {
 #define GKB_INNER_LEARNED 2  /* flexible CG, preconditioner = V-cycle + CNN
                                 correction, falling back to MG-PCG */
 
+/* Krylov method of the inner solves (the preconditioner is chosen by
+   `inner`: diag(M)^-1 for GKB_INNER_JACOBI, one V-cycle for GKB_INNER_MG).
+   Section 3 leaves the inner Krylov method to the user; Section 4.1.3
+   compares CG and fgmres. */
+#define GKB_KRYLOV_CG 0      /* preconditioned CG (flexible CG for _LEARNED) */
+#define GKB_KRYLOV_FGMRES 1  /* restarted flexible GMRES, right preconditioned,
+                                restart fgmres_restart; stops on the same
+                                relative residual as CG */
+
+/* how gkb_solve uses GKB (Section 3: GKB as a solver or as a preconditioner) */
+#define GKB_METHOD_SOLVER 0  /* GKB runs (with defect correction when
+                                refine_tol > 0) */
+#define GKB_METHOD_PRECOND 1 /* restarted flexible GMRES on the whole saddle
+                                system (1), right preconditioned by one GKB run
+                                (lower-bound tol, delay, maxit) per iteration;
+                                stops when the FP64 relative saddle residual is
+                                <= refine_tol (> 0 required) or after
+                                max_sweeps iterations (GKB_MAXIT) */
+
 /* multigrid smoother */
 #define GKB_SMOOTH_JACOBI 0  /* weighted Jacobi on M */
 #define GKB_SMOOTH_HYBRID 1  /* weighted Jacobi on M, each sweep paired with a
@@ -116,6 +135,24 @@ typedef struct {
   void *hip_stream;     /* hipStream_t; NULL = null stream */
   size_t max_workspace_bytes; /* 0 = unlimited; else setup fails with
                                  GKB_ENOMEM above this device footprint */
+  int krylov;           /* GKB_KRYLOV_CG or GKB_KRYLOV_FGMRES (inner solves;
+                           FGMRES with GKB_INNER_JACOBI or _MG only) */
+  int fgmres_restart;   /* Krylov vectors of the inner FGMRES (1..64) */
+  int method;           /* GKB_METHOD_SOLVER or GKB_METHOD_PRECOND */
+  int outer_restart;    /* Krylov vectors of the outer FGMRES of
+                           GKB_METHOD_PRECOND (1..32) */
+  const char *cnn_weights; /* NULL, or the path of a network checkpoint
+                              (gkb_cnn_save) loaded at setup and owned by the
+                              context; used by GKB_INNER_LEARNED (the same as
+                              gkb_attach_cnn with a network the context frees).
+                              A file that does not load, or whose network does
+                              not fit the grid, fails setup with GKB_EINVAL */
+  double learned_min_gain; /* GKB_INNER_LEARNED: the network correction is
+                              dropped (fallback to MG-PCG) when the error energy
+                              its step removes falls below this fraction of the
+                              V-cycle step's (gkb_stats_t.learned_gain); <= 0
+                              turns this test off (the descent and progress
+                              tests stay) */
 } gkb_options;
 
 typedef struct {
@@ -145,14 +182,24 @@ typedef struct {
                              gkb_solve of the error energy removed by the
                              network step relative to the V-cycle step,
                              (c.rt)^2 / (c.Mc) / (r.V(r)); -1 if none.  Below
-                             0.05 an inner solve falls back to MG-PCG */
+                             learned_min_gain an inner solve falls back to
+                             MG-PCG */
+  int learned_fallback_reason;    /* cause of the last fallback of the last
+                                     gkb_solve: 0 none, 1 descent (r.z <= 0),
+                                     2 no progress over 50 iterations, 3 gain
+                                     below learned_min_gain */
+  int learned_fallback_iteration; /* inner iteration of that fallback */
+  int outer_krylov_iterations;    /* GKB_METHOD_PRECOND: outer FGMRES
+                                     iterations (= GKB runs) of the last solve */
 } gkb_stats_t;
 
 typedef struct gkb_ctx gkb_ctx;
 
 /* Fill *opt with defaults: FP64, MG inner, auto levels, V(2,2), Jacobi
    smoother, inner_tol 1e-10, inner_maxit 10000, maxit 500, refine_tol 0,
-   max_sweeps 10, check_every 8, graphs on, null stream. */
+   max_sweeps 10, check_every 8, graphs on, null stream, CG inner solves,
+   fgmres_restart 30, GKB as the solver, outer_restart 10, no network file,
+   learned_min_gain 0.05. */
 void gkb_default_options(gkb_options *opt);
 
 /* Create a context for one grid, viscosity field and eta (the paper's nu).
@@ -161,14 +208,16 @@ void gkb_default_options(gkb_options *opt);
    builds the multigrid hierarchy (coarsened viscosity, Jacobi weights, dense
    FP64 inverse of the coarsest operator).  Errors: GKB_EINVAL (dim not 2/3,
    n < 2, h <= 0, eta < 0, bad bc, pin out of range, grid not divisible for
-   mg_levels, M singular because every side is NATURAL), GKB_ENOMEM, GKB_EHIP. */
+   mg_levels, M singular because every side is NATURAL, an option out of
+   range, cnn_weights that does not load or fit), GKB_ENOMEM, GKB_EHIP. */
 int gkb_setup(const gkb_grid *grid, const double *viscosity, double eta,
               const gkb_options *opt, gkb_ctx **out);
 
 /* Solve (1) for the right-hand sides g (faces) and r (cells), all device FP64.
    tol = tau of the lower-bound rule (Section 2.2; stop when the ratio of the
    newest delay+1 squared zeta values to all of them is <= tol^2; tol <= 0 runs
-   maxit steps).  delay = d >= 0.  Writes w (faces) and p (cells); iterations
+   maxit steps).  delay = d >= 1 (the window holds d+1 values; d < 1 is
+   GKB_EINVAL).  Writes w (faces) and p (cells); iterations
    (may be NULL) receives K of the last sweep, error_estimate (may be NULL)
    the last lower-bound ratio.  g and w, r and p may not alias.
    Returns GKB_OK, GKB_MAXIT, GKB_ENAN, GKB_EINNER, GKB_EINVAL, GKB_EHIP. */
@@ -185,6 +234,46 @@ int gkb_sizes(const gkb_ctx *c, long *m_full, long *n_cells, long *m_unknown,
 const char *gkb_strerror(int code);
 
 void gkb_destroy(gkb_ctx *c);
+
+/* ---- assembled systems ------------------------------------------------ */
+
+/* A saddle system given by its blocks as compressed sparse rows, the form a
+   PETSc fieldsplit user passes (Section 3): W (m x m, symmetric positive
+   definite, or semidefinite with eta > 0 making M definite) and A (m x n,
+   full column rank).  All arrays are HOST arrays, copied at setup; column
+   indices 0-based and in range; every diagonal entry of W must be present and
+   positive. */
+typedef struct {
+  int m;                  /* velocity unknowns: rows of W and of A */
+  int n;                  /* pressure unknowns: columns of A */
+  const int *w_rowptr;    /* m + 1 row offsets of W, w_rowptr[0] = 0 */
+  const int *w_col;       /* w_rowptr[m] column indices of W */
+  const double *w_val;    /* w_rowptr[m] values of W */
+  const int *a_rowptr;    /* m + 1 row offsets of A */
+  const int *a_col;       /* a_rowptr[m] column indices of A (< n) */
+  const double *a_val;
+} gkb_csr;
+
+#define GKB_SCALE_NONE 0     /* solve the system as given */
+#define GKB_SCALE_CENTRAL 1  /* solve the system scaled on both sides by
+                                blockdiag(D^-1/2, R^-1/2), D = diag(W),
+                                R = diag(A^T D^-1 A) (the central scaling of
+                                Section 4.1, which equilibrates the blocks);
+                                the solution is scaled back, so w and p solve
+                                the given system */
+
+/* Context for an assembled system (otherwise as gkb_setup).  The inner
+   solver must be GKB_INNER_JACOBI (CG or FGMRES; multigrid needs a grid);
+   opt == NULL selects it with the other defaults.  gkb_solve takes g (m) and
+   r (n) and writes w (m) and p (n), device FP64; with central scaling its
+   lower-bound rule, the defect-correction residual (refine_tol) and
+   gkb_stats_t.residual refer to the scaled system, while gkb_residual
+   evaluates the given one; gkb_apply applies the scaled operators.
+   Errors: GKB_EINVAL (bad sizes, indices, values, a non-positive diagonal
+   of W, an empty column of A with scaling, eta < 0, a multigrid or learned
+   inner solver), GKB_ENOMEM, GKB_EHIP. */
+int gkb_setup_csr(const gkb_csr *sys, double eta, int scaling, const gkb_options *opt,
+                  gkb_ctx **out);
 
 /* ---- operator-level entry points (used by the parity tests) ----------- */
 

@@ -14,7 +14,7 @@ import ctypes as C
 
 from . import _abi
 
-__all__ = ["Solver", "library", "CNN"]
+__all__ = ["Solver", "CsrSolver", "library", "CNN"]
 
 
 def library():
@@ -45,31 +45,21 @@ class Solver:
     mu: host array of cell viscosities (numpy / CPU tensor) or None (mu = 1).
     eta: augmented-Lagrangian parameter (the paper's nu; 0 = off).
     options: precision ("fp64" | "mixed"), inner ("jacobi" | "mg" | "learned"),
-      smoother ("jacobi" | "hybrid"), mg_levels, nu_pre, nu_post, inner_tol, inner_maxit, maxit, refine_tol,
-      max_sweeps, check_every, use_graphs, max_workspace_bytes.
+      smoother ("jacobi" | "hybrid"), krylov ("cg" | "fgmres"), fgmres_restart,
+      method ("solver" | "precond": GKB as the solver or as the preconditioner
+      of an outer FGMRES), outer_restart, cnn_weights (checkpoint path loaded at
+      setup), learned_min_gain, mg_levels, nu_pre, nu_post, inner_tol,
+      inner_maxit, maxit, refine_tol, max_sweeps, check_every, use_graphs,
+      stencil, max_workspace_bytes.
     """
 
     def __init__(self, grid, mu=None, eta=0.0, **options):
         import numpy as np
-        import torch
 
         L = _abi.lib()
         self.grid = grid
         self.eta = float(eta)
-        opt = _abi.Options()
-        L.gkb_default_options(C.byref(opt))
-        for k, v in options.items():
-            if k == "precision":
-                v = {"fp64": _abi.FP64, "mixed": _abi.MIXED}.get(v, v)
-            elif k == "inner":
-                v = _abi.INNER.get(v, v)
-            elif k == "smoother":
-                v = _abi.SMOOTHERS.get(v, v)
-            if not hasattr(opt, k):
-                raise TypeError(f"unknown option {k}")
-            setattr(opt, k, v)
-        self.options = {f: getattr(opt, f) for f, _ in _abi.Options._fields_}
-        opt.hip_stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        opt = self._options(options)
         self._mu = None
         mu_ptr = None
         if mu is not None:
@@ -79,6 +69,39 @@ class Solver:
         gs = _grid_struct(grid)
         _abi.check(L.gkb_setup(C.byref(gs), mu_ptr, self.eta, C.byref(opt), C.byref(ctx)),
                    "gkb_setup")
+        self._finish(ctx)
+
+    def _options(self, options, defaults=None):
+        import torch
+
+        L = _abi.lib()
+        opt = _abi.Options()
+        L.gkb_default_options(C.byref(opt))
+        for k, v in dict(defaults or {}, **options).items():
+            if k == "precision":
+                v = {"fp64": _abi.FP64, "mixed": _abi.MIXED}.get(v, v)
+            elif k == "inner":
+                v = _abi.INNER.get(v, v)
+            elif k == "smoother":
+                v = _abi.SMOOTHERS.get(v, v)
+            elif k == "krylov":
+                v = _abi.KRYLOV.get(v, v)
+            elif k == "method":
+                v = _abi.METHODS.get(v, v)
+            elif k == "cnn_weights":
+                v = None if v is None else str(v).encode()
+            if not hasattr(opt, k):
+                raise TypeError(f"unknown option {k}")
+            setattr(opt, k, v)
+        self.options = {f: getattr(opt, f) for f, _ in _abi.Options._fields_}
+        self._weights_path = opt.cnn_weights  # kept alive through gkb_setup
+        opt.hip_stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        return opt
+
+    def _finish(self, ctx):
+        import torch
+
+        L = _abi.lib()
         self._ctx = ctx
         m_full, n_cells, mu_n, nu_n = (C.c_long() for _ in range(4))
         L.gkb_sizes(ctx, C.byref(m_full), C.byref(n_cells), C.byref(mu_n), C.byref(nu_n))
@@ -139,7 +162,10 @@ class Solver:
                     estimate=list(st.estimate[:n]), workspace_bytes=st.workspace_bytes,
                     mg_levels=st.mg_levels, omega=list(st.omega[:st.mg_levels]),
                     omega_edge=list(st.omega_edge[:st.mg_levels]),
-                    learned_gain=st.learned_gain)
+                    learned_gain=st.learned_gain,
+                    learned_fallback_reason=st.learned_fallback_reason,
+                    learned_fallback_iteration=st.learned_fallback_iteration,
+                    outer_krylov_iterations=st.outer_krylov_iterations)
 
     def apply(self, op, x, precision="fp64"):
         """y = op(x) for op in W, A, AT, M, diag (gkb_apply)."""
@@ -199,6 +225,46 @@ class Solver:
         _abi.check(_abi.lib().gkb_residual(self._ctx, _ptr(g), _ptr(r), _ptr(w), _ptr(p),
                                            _ptr(rw), _ptr(rr), norms), "gkb_residual")
         return list(norms), rw, rr
+
+
+class CsrSolver(Solver):
+    """A solver context for an assembled saddle system (gkb_setup_csr).
+
+    W: m x m and A: m x n scipy.sparse matrices (any format; converted to
+    CSR with int32 indices), eta as for Solver, scaling "central" (the
+    block scaling blockdiag(D^-1/2, R^-1/2) of Section 4.1) or "none".  The
+    inner solver is Jacobi-preconditioned CG (krylov="cg") or FGMRES.
+    solve(g, r) takes and returns cuda float64 tensors of lengths m and n."""
+
+    def __init__(self, W, A, eta=0.0, scaling="central", **options):
+        import numpy as np
+
+        L = _abi.lib()
+        self.grid = None
+        self.eta = float(eta)
+        m, n = A.shape
+        if W.shape != (m, m):
+            raise ValueError("W must be m x m and A m x n")
+        opt = self._options(options, defaults=dict(inner="jacobi"))
+        keep = []
+        sysd = _abi.Csr()
+        sysd.m, sysd.n = int(m), int(n)
+        for name, M in (("w", W), ("a", A)):
+            M = M.tocsr()
+            M.sort_indices()
+            ptr = np.ascontiguousarray(M.indptr, dtype=np.int32)
+            col = np.ascontiguousarray(M.indices, dtype=np.int32)
+            val = np.ascontiguousarray(M.data, dtype=np.float64)
+            keep += [ptr, col, val]
+            setattr(sysd, name + "_rowptr", ptr.ctypes.data_as(C.POINTER(C.c_int)))
+            setattr(sysd, name + "_col", col.ctypes.data_as(C.POINTER(C.c_int)))
+            setattr(sysd, name + "_val", val.ctypes.data_as(C.POINTER(C.c_double)))
+        mode = {"none": _abi.SCALE_NONE, "central": _abi.SCALE_CENTRAL}[scaling]
+        ctx = C.c_void_p()
+        _abi.check(L.gkb_setup_csr(C.byref(sysd), self.eta, mode, C.byref(opt), C.byref(ctx)),
+                   "gkb_setup_csr")
+        del keep
+        self._finish(ctx)
 
 
 from .cnn import CNN  # noqa: E402

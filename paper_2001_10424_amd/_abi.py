@@ -16,10 +16,21 @@ INNER = {"jacobi": 0, "mg": 1, "learned": 2}
 OPS = {"W": 0, "A": 1, "AT": 2, "M": 3, "diag": 4}
 KERNELS = {"smooth": 0, "apply": 1, "resid": 2, "smooth_prolong": 3, "smooth_zero": 4}
 SMOOTHERS = {"jacobi": 0, "hybrid": 1}
+KRYLOV = {"cg": 0, "fgmres": 1}
+METHODS = {"solver": 0, "precond": 1}
+SCALE_NONE, SCALE_CENTRAL = 0, 1
 
 class Grid(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("h", C.c_double),
                 ("bc", C.c_int * 6), ("pin_cell", C.c_int)]
+
+
+class Csr(C.Structure):
+    _fields_ = [("m", C.c_int), ("n", C.c_int),
+                ("w_rowptr", C.POINTER(C.c_int)), ("w_col", C.POINTER(C.c_int)),
+                ("w_val", C.POINTER(C.c_double)),
+                ("a_rowptr", C.POINTER(C.c_int)), ("a_col", C.POINTER(C.c_int)),
+                ("a_val", C.POINTER(C.c_double))]
 
 
 class Options(C.Structure):
@@ -28,7 +39,10 @@ class Options(C.Structure):
                 ("inner_maxit", C.c_int), ("maxit", C.c_int), ("refine_tol", C.c_double),
                 ("max_sweeps", C.c_int), ("check_every", C.c_int), ("use_graphs", C.c_int),
                 ("stencil", C.c_int), ("smoother", C.c_int),
-                ("hip_stream", C.c_void_p), ("max_workspace_bytes", C.c_size_t)]
+                ("hip_stream", C.c_void_p), ("max_workspace_bytes", C.c_size_t),
+                ("krylov", C.c_int), ("fgmres_restart", C.c_int), ("method", C.c_int),
+                ("outer_restart", C.c_int), ("cnn_weights", C.c_char_p),
+                ("learned_min_gain", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -39,7 +53,9 @@ class Stats(C.Structure):
                 ("history_len", C.c_int), ("zeta", C.c_double * 512),
                 ("estimate", C.c_double * 512), ("workspace_bytes", C.c_size_t),
                 ("mg_levels", C.c_int), ("omega", C.c_double * 16),
-                ("omega_edge", C.c_double * 16), ("learned_gain", C.c_double)]
+                ("omega_edge", C.c_double * 16), ("learned_gain", C.c_double),
+                ("learned_fallback_reason", C.c_int), ("learned_fallback_iteration", C.c_int),
+                ("outer_krylov_iterations", C.c_int)]
 
 
 _lib = None
@@ -81,6 +97,9 @@ def lib():
     L.gkb_residual.restype = C.c_int
     L.gkb_time_kernel.argtypes = [ctxp, C.c_int, C.c_int, C.POINTER(C.c_double)]
     L.gkb_time_kernel.restype = C.c_int
+    L.gkb_setup_csr.argtypes = [C.POINTER(Csr), C.c_double, C.c_int, C.POINTER(Options),
+                                C.POINTER(ctxp)]
+    L.gkb_setup_csr.restype = C.c_int
     _declare_cnn(L)
     _lib = L
     return L

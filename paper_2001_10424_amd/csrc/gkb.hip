@@ -1,18 +1,18 @@
 // Host runtime and C-ABI of the GKB solver (see include/gkb.h).
 //
-// Structure of one gkb_solve (paper Section 2, Algorithm 1):
-//   transformation  ghat = g + eta A r ; w0 = M^-1 ghat ; b = r - A^T w0
-//   initialisation  beta_1 = ||b||_{N^-1}, q_1 = N^-1 b / beta_1,
-//                   s = M^-1 A q_1, alpha_1 = ||s||_M, ...
-//   loop            t = N^-1 A^T v - alpha q, beta = ||t||_N, q = t / beta,
-//                   s = M^-1 (A q - beta M v), alpha = ||s||_M,
-//                   zeta = -(beta/alpha) zeta, d = (q - beta d)/alpha,
-//                   u += zeta v, p -= zeta d, lower-bound test with delay d.
-// The scalars of the outer recurrence live on the host in FP64; every vector
-// operation is a HIP kernel.  The inner solves M x = f (the dominant cost)
-// are PCG / flexible CG iterations whose scalars stay on the device; chunks
-// of iterations are captured in HIP graphs and replayed until the device-side
-// convergence flag is set (iterations after convergence are no-ops).
+// One gkb_solve runs generalized Golub-Kahan bidiagonalization (Section 2):
+// the change of variables that leaves a zero first right-hand side, then
+// columns of the bidiagonal B from the relations A Q = M V B and
+// A^T V = N Q B^T, each needing one inner solve with M = W + eta A A^T,
+// turned into the Craig-variant iterates (u, p) and stopped by the delayed
+// lower bound of Section 2.2.  Optional around it: defect correction in FP64
+// (mixed precision), or an outer FGMRES that uses the GKB run as its
+// preconditioner (Section 3).  The scalars of the outer recurrence live on
+// the host in FP64; every vector operation is a HIP kernel.  The inner
+// solves (the dominant cost) are PCG, flexible CG or FGMRES iterations whose
+// scalars stay on the device; chunks of iterations are captured in HIP
+// graphs and replayed until the device-side convergence flag is set
+// (iterations after convergence are no-ops).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,6 +30,8 @@
 #include "learned.hpp"
 #include "tile3d.hpp"
 #include "hybrid.hpp"
+#include "fgmres.hpp"
+#include "csr.hpp"
 
 using namespace gkb;
 
@@ -53,6 +55,8 @@ namespace {
 
 constexpr int kMaxLevels = 16;
 constexpr int kSlots = 6;
+constexpr int kMaxRestart = kGmMaxRestart;  // inner FGMRES Krylov vectors
+constexpr int kMaxOuterRestart = 32;  // outer FGMRES (GKB as preconditioner)
 
 int vec_blocks(int n) { return std::max(1, std::min((n + 1023) / 1024, 4096)); }
 
@@ -66,8 +70,6 @@ struct FaceLaunch {
   int tz = 8;
 };
 
-int g_tz = 0;  // z-planes per tiled block (0: default)
-
 FaceLaunch face_launch(const Grid& g, int kz, int stencil = 0) {
   FaceLaunch L;
   int maxplane = 0;
@@ -80,24 +82,15 @@ FaceLaunch face_launch(const Grid& g, int kz, int stencil = 0) {
   // the tiled kernel covers the lower faces of every cell: the upper faces
   // must be Dirichlet (zero) faces
   const bool upper_dir = g.bc[1] == kDir && g.bc[3] == kDir && g.bc[5] == kDir;
-  static const long tile_min = [] {
-    const char* e = std::getenv("GKB_TILE_MIN");
-    return e ? std::atol(e) : 0L;
-  }();
   // (32-bit buffer offsets: face arrays below 2 GiB in FP64)
-  if (stencil == 0 && g.dim == 3 && upper_dir && g.n_cells >= tile_min &&
-      (long)g.m_full * 8 < (1L << 31)) {
-    if (g_tz == 0) {
-      const char* e = std::getenv("GKB_TZ");
-      g_tz = e ? std::max(1, std::atoi(e)) : -1;
-    }
+  if (stencil == 0 && g.dim == 3 && upper_dir && (long)g.m_full * 8 < (1L << 31)) {
     L.tiled = true;
     const int tx = (g.n[0] + kTX - 1) / kTX, ty = (g.n[1] + kTY - 1) / kTY;
     // z-planes per block: keep >= ~512 blocks in flight; more planes per
     // block amortise the z-halo and the block set-up but starve small grids
     // (128^3: 8 planes, 1024 blocks, where 2, 4 and 16 were slower; 64^3: 2
     // planes, 512 blocks, 1-3 % faster MG-PCG iterations than 1 or 4)
-    int tz = g_tz > 0 ? g_tz : std::max(1, std::min(8, tx * ty * g.n[2] / 512));
+    const int tz = std::max(1, std::min(8, tx * ty * g.n[2] / 512));
     L.tz = std::min(tz, g.n[2]);
     L.tgrid = dim3(tx, ty, (g.n[2] + L.tz - 1) / L.tz);
     L.nparts = L.tgrid.x * L.tgrid.y * L.tgrid.z;
@@ -186,6 +179,14 @@ struct Inner {
   int graph_mode = -1;
   hipGraphExec_t graph_fcg = nullptr;
   int graph_fcg_len = 0;
+  // inner FGMRES: basis V (restart + 1 vectors) and preconditioned vectors Z
+  // (restart), FP64 Hessenberg state, the cycle flag and the dot partials;
+  // one restart cycle is one captured graph
+  T *gm_V = nullptr, *gm_Z = nullptr;
+  FgmState* gm_fs = nullptr;
+  PcgState* gm_cyc = nullptr;
+  double* gm_part = nullptr;
+  hipGraphExec_t graph_gm = nullptr;
 };
 
 }  // namespace
@@ -216,6 +217,10 @@ struct gkb_ctx {
   double *ghat = nullptr, *w0 = nullptr, *u = nullptr, *v = nullptr, *Mv = nullptr, *s = nullptr,
          *y = nullptr, *f = nullptr, *rw = nullptr, *dw = nullptr;
   double *wbest = nullptr, *pbest = nullptr;  // best defect-correction iterate
+  // GKB as the preconditioner of an outer FGMRES: basis V (outer_restart + 1)
+  // and preconditioned vectors Z (outer_restart), each a (faces | cells)
+  // pair of m_full + n_cells doubles, and a zero pair
+  double *ov = nullptr, *oz = nullptr, *ozero = nullptr;
   double *b = nullptr, *q = nullptr, *d = nullptr, *t = nullptr, *rr = nullptr, *dp = nullptr;
   double* part[kSlots] = {nullptr};
   int maxparts = 0;
@@ -224,17 +229,64 @@ struct gkb_ctx {
   FaceLaunch fl0;
   gkb_stats_t stats;
   Learned* learned = nullptr;
+  gkb_cnn* owned_net = nullptr;  // network loaded from opt.cnn_weights
+  // assembled (CSR) system instead of the MAC grid: operators, A'^T x
+  // temporaries per precision, central-scaling state and scaled right-hand
+  // sides
+  bool csr = false;
+  bool csr_scaled = false;
+  CsrOps<double> csr64;
+  CsrOps<float> csr32;
+  double* csr_t64 = nullptr;
+  float* csr_t32 = nullptr;
+  double *csr_gs = nullptr, *csr_rs = nullptr;
 };
 
 namespace {
 
 // ------------------------------------------------------------ launches
 
+template <typename T>
+const CsrOps<T>& csr_of(const gkb_ctx* c);
+template <>
+const CsrOps<double>& csr_of<double>(const gkb_ctx* c) { return c->csr64; }
+template <>
+const CsrOps<float>& csr_of<float>(const gkb_ctx* c) { return c->csr32; }
+template <typename T>
+T* csr_tmp(gkb_ctx* c);
+template <>
+double* csr_tmp<double>(gkb_ctx* c) { return c->csr_t64; }
+template <>
+float* csr_tmp<float>(gkb_ctx* c) { return c->csr_t32; }
+
+// the M-apply modes on an assembled system (t = A'^T x first)
+template <typename T, int MODE>
+void csr_face_op(gkb_ctx* c, T eta, const T* x, const T* b, T* y, double* partial,
+                 const PcgState* st) {
+  const CsrOps<T>& o = csr_of<T>(c);
+  hipStream_t s = c->cs;
+  if constexpr (MODE == kApply || MODE == kApplyDot || MODE == kResid || MODE == kResidDot ||
+                MODE == kDiag) {
+    T* t = csr_tmp<T>(c);
+    if (MODE != kDiag && eta != T(0)) k_csr_at<T><<<vec_blocks(o.n), kBlock, 0, s>>>(o, x, t, st);
+    k_csr_m<T, MODE><<<vec_blocks(o.m), kBlock, 0, s>>>(o, eta, x, t, b, y, partial, st);
+  }
+}
+
+// partials written by the A^T kernel (div_axpy)
+int div_parts(const gkb_ctx* c) {
+  return c->csr ? vec_blocks(c->g.n_cells) : cell_parts(c->g);
+}
+
 // ec / Gc: coarse correction and coarse grid of kJacobiP (unused otherwise)
 template <typename T, int MODE>
 void face_op(gkb_ctx* c, const Op<T>& op, const FaceLaunch& fl, const T* x, const T* b, T* y,
              T omega, double* partial, const PcgState* st, const T* ec = nullptr,
              const Grid* Gc = nullptr, T* y2 = nullptr) {
+  if (c->csr) {
+    csr_face_op<T, MODE>(c, op.eta, x, b, y, partial, st);
+    return;
+  }
   const bool vm = op.mu != nullptr;
   const int kz = fl.kz, zc = fl.zchunks;
   hipStream_t s = c->cs;
@@ -269,6 +321,10 @@ void face_op(gkb_ctx* c, const Op<T>& op, const FaceLaunch& fl, const T* x, cons
 }
 
 void grad_axpy(gkb_ctx* c, const double* q, const double* yv, double s1, double s2, double* out) {
+  if (c->csr) {
+    k_csr_grad<<<vec_blocks(c->g.m_full), kBlock, 0, c->cs>>>(c->csr64, q, yv, s1, s2, out);
+    return;
+  }
   const FaceLaunch& fl = c->fl0;
   if (c->g.dim == 2)
     k_grad_axpy<2><<<fl.grid, kBlock, 0, c->cs>>>(c->g, q, yv, s1, s2, out, fl.kz, fl.zchunks);
@@ -279,6 +335,11 @@ void grad_axpy(gkb_ctx* c, const double* q, const double* yv, double s1, double 
 template <typename T>
 void div_axpy(gkb_ctx* c, const Grid& g, const T* x, const T* z, double s1, double s2, T* t,
               double* partial, double* zz) {
+  if (c->csr) {
+    k_csr_div<T><<<vec_blocks(g.n_cells), kBlock, 0, c->cs>>>(csr_of<T>(c), x, z, s1, s2, t,
+                                                               partial, zz);
+    return;
+  }
   if (g.dim == 2)
     k_div_axpy<T, 2><<<cell_grid(g), kBlock, 0, c->cs>>>(g, x, z, s1, s2, t, partial, zz);
   else
@@ -489,11 +550,92 @@ int ensure_graph(gkb_ctx* c, Inner<T>& in, int count) {
   return GKB_OK;
 }
 
+// One restart cycle of the inner FGMRES (fgmres.hpp): Arnoldi steps
+// j = 0 .. restart-1 with z_j = P(v_j) (Jacobi or one V-cycle) and
+// w = M z_j orthogonalised by two classical Gram-Schmidt passes, then
+// x += Z y, and the next cycle's start from the true residual r = f - M x
+// (f in in.rprev).  Every kernel skips once its flag is set, so the launch
+// sequence is fixed and is captured as one graph.
+template <typename T>
+void fgmres_cycle(gkb_ctx* c, Inner<T>& in) {
+  const Level<T>& L0 = in.lv[0];
+  const int n = L0.g.m_full, vb = vec_blocks(n);
+  const int R = c->opt.fgmres_restart;
+  const long ld = n;
+  hipStream_t s = c->cs;
+  const bool jac = c->opt.inner == GKB_INNER_JACOBI;
+  for (int j = 0; j < R; ++j) {
+    T* vj = in.gm_V + j * ld;
+    T* zj = in.gm_Z + j * ld;
+    T* w = in.gm_V + (j + 1) * ld;
+    if (jac) k_gm_jacobi<T><<<vb, kBlock, 0, s>>>(n, in.gm_cyc, in.dinv, vj, zj);
+    else vcycle<T>(c, in, 0, vj, zj, nullptr, in.gm_cyc);
+    face_op<T, kApply>(c, L0.op, L0.fl, zj, nullptr, w, T(0), nullptr, in.gm_cyc);
+    const int nv = j + 1;
+    const dim3 dg(vb, (nv + kGmChunk - 1) / kGmChunk);
+    for (int pass = 0; pass < 2; ++pass) {
+      k_gm_mdot<T><<<dg, kBlock, 0, s>>>(n, in.gm_cyc, in.gm_V, ld, nv, w, in.gm_part);
+      k_gm_hsum<<<1, kFinal, 0, s>>>(in.gm_cyc, in.gm_fs, in.gm_part, vb, nv, j, pass);
+      k_gm_maxpy<T><<<vb, kBlock, 0, s>>>(n, in.gm_cyc, in.gm_fs, in.gm_V, ld, nv, w, c->part[0]);
+    }
+    k_gm_arnoldi_end<<<1, kFinal, 0, s>>>(in.st, in.gm_cyc, in.gm_fs, c->part[0], vb, j,
+                                          j == R - 1 ? 1 : 0);
+    k_gm_scale<T><<<vb, kBlock, 0, s>>>(n, in.gm_cyc, in.gm_fs, j, w);
+  }
+  k_gm_solve_y<<<1, 64, 0, s>>>(in.st, in.gm_fs);
+  k_gm_update_x<T><<<vb, kBlock, 0, s>>>(n, in.st, in.gm_fs, in.gm_Z, ld, in.x);
+  k_gm_cycle_end<<<1, 64, 0, s>>>(in.st, in.gm_fs);
+  face_op<T, kResidDot>(c, L0.op, L0.fl, in.x, in.rprev, in.r, T(0), c->part[1], in.st);
+  k_gm_start<<<1, kFinal, 0, s>>>(in.st, in.gm_cyc, in.gm_fs, c->part[1], L0.fl.nparts, 0.0, 0, 0);
+  k_gm_v0<T><<<vb, kBlock, 0, s>>>(n, in.st, in.gm_fs, in.r, in.gm_V);
+}
+
+template <typename T>
+int fgmres_solve(gkb_ctx* c, const double* f, double* x_out, double tol, int* iters) {
+  Inner<T>& in = inner_of<T>(c);
+  const int n = in.lv[0].g.m_full, vb = vec_blocks(n);
+  hipStream_t s = c->cs;
+  k_pcg_init<double, T><<<vb, kBlock, 0, s>>>(n, f, in.x, in.r, c->part[3]);
+  k_cast<T, T><<<vb, kBlock, 0, s>>>(n, in.r, in.rprev);  // f in working precision
+  k_gm_start<<<1, kFinal, 0, s>>>(in.st, in.gm_cyc, in.gm_fs, c->part[3], vb, tol,
+                                  c->opt.inner_maxit, 1);
+  k_gm_v0<T><<<vb, kBlock, 0, s>>>(n, in.st, in.gm_fs, in.r, in.gm_V);
+  if (c->opt.use_graphs && !in.graph_gm) {
+    hipGraph_t gr;
+    HIPCK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    fgmres_cycle<T>(c, in);
+    HIPCK(hipStreamEndCapture(s, &gr));
+    const hipError_t ie = hipGraphInstantiate(&in.graph_gm, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    HIPCK(ie);
+  }
+  PcgState hs;
+  // every cycle takes at least one Arnoldi step, so inner_maxit bounds the
+  // number of cycles
+  for (long cyc = 0; cyc <= (long)c->opt.inner_maxit; ++cyc) {
+    if (c->opt.use_graphs) HIPCK(hipGraphLaunch(in.graph_gm, s));
+    else fgmres_cycle<T>(c, in);
+    HIPCK(hipMemcpyAsync(c->hbuf, in.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    std::memcpy(&hs, c->hbuf, sizeof(PcgState));
+    if (hs.done) break;
+  }
+  k_cast<T, double><<<vb, kBlock, 0, s>>>(n, in.x, x_out);
+  if (iters) *iters = hs.it;
+  c->stats.inner_iterations += hs.it;
+  c->stats.inner_solves += 1;
+  if (hs.nonfinite) return GKB_ENAN;
+  if (!hs.done || hs.status == -5) return GKB_EINNER;
+  return GKB_OK;
+}
+
 // x_out = M^-1 f (FP64 in and out; T = working precision of the inner solve)
 template <typename T>
 int inner_solve(gkb_ctx* c, const double* f, double* x_out, double tol, int* iters) {
   Inner<T>& in = inner_of<T>(c);
   if (!in.ready) return GKB_EINVAL;
+  if (c->opt.krylov == GKB_KRYLOV_FGMRES && !learned_capturing(c->learned))
+    return fgmres_solve<T>(c, f, x_out, tol, iters);
   if (learned_capturing(c->learned) && c->opt.inner != GKB_INNER_JACOBI)
     return capture_solve<T>(c, f, x_out, tol, iters);
   if (c->opt.inner == GKB_INNER_LEARNED && c->learned && learned_enabled(c->learned)) {
@@ -540,100 +682,158 @@ int inner_solve_any(gkb_ctx* c, const double* f, double* x, double tol, int* ite
 }
 
 // ---------------------------------------------------------------- GKB
+//
+// The run is organised around the generalized Golub-Kahan relations
+// A Q = M V B, A^T V = N Q B^T, V^T M V = I, Q^T N Q = I (Section 2.1),
+// N = (1/eta) I (eta > 0) or I: a bidiagonalization step produces the next
+// coefficients (alpha, beta) and the M-normalised v with M v, and the
+// Craig-variant update turns them into the iterates u, p through
+// zeta and the direction d.  Host FP64 scalars, device vectors.
 
-// One GKB run (Algorithm 1 with the transformation of Section 2) for the
-// right-hand sides (gv, rv); writes w, p.
-int gkb_run(gkb_ctx* c, const double* gv, const double* rv, double tol, int delay, double* w,
-            double* p, int* K_out, double* est_out) {
+struct GkScalars {
+  double ninv = 1.0;   // N^-1 = ninv I
+  double alpha = 0.0;  // alpha_k
+  double beta = 0.0;   // beta_k (beta_1 = ||b||_{N^-1})
+  double zeta = 0.0;   // zeta_k
+};
+
+// transformation to a zero first right-hand side (Section 2):
+// w0 = M^-1 (g + gamma A N^-1 r) (skipped when that is 0), b = r - A^T w0;
+// returns beta_1 = ||b||_{N^-1}
+int gk_transform(gkb_ctx* c, const double* gv, const double* rv, double ninv, double* beta1) {
   const Grid& G = c->g;
-  const int m = G.m_full, nc = G.n_cells, vbm = vec_blocks(m), vbc = vec_blocks(nc);
+  const int m = G.m_full;
   hipStream_t s = c->cs;
-  const double eta = c->eta;
-  const double ninv = eta > 0.0 ? eta : 1.0;
-  const double itol = c->opt.inner_tol;
   int its = 0;
-  // ghat = g + gamma A N^-1 r (masked)
-  grad_axpy(c, rv, gv, eta, 1.0, c->ghat);
-  k_dot<double><<<vbm, kBlock, 0, s>>>(m, c->ghat, c->ghat, c->part[0]);
+  grad_axpy(c, rv, gv, c->eta, 1.0, c->ghat);  // ghat = g + eta A r (masked)
+  k_dot<double><<<vec_blocks(m), kBlock, 0, s>>>(m, c->ghat, c->ghat, c->part[0]);
   double gg = 0.0;
-  CK(host_sum(c, c->part[0], vbm, &gg));
+  CK(host_sum(c, c->part[0], vec_blocks(m), &gg));
   if (!std::isfinite(gg)) return GKB_ENAN;
-  if (gg == 0.0) {
-    k_fill<double><<<vbm, kBlock, 0, s>>>(m, 0.0, c->w0);
-  } else {
-    CK(inner_solve_any(c, c->ghat, c->w0, itol, &its));
-  }
-  // b = r - A^T w0, beta_1 = sqrt(b . N^-1 b)
+  if (gg == 0.0) k_fill<double><<<vec_blocks(m), kBlock, 0, s>>>(m, 0.0, c->w0);
+  else CK(inner_solve_any(c, c->ghat, c->w0, c->opt.inner_tol, &its));
   div_axpy<double>(c, G, c->w0, rv, -1.0, 1.0, c->b, c->part[0], nullptr);
   double bb = 0.0;
-  CK(host_sum(c, c->part[0], cell_parts(G), &bb));
-  const double beta1 = std::sqrt(ninv * bb);
-  if (!std::isfinite(beta1)) return GKB_ENAN;
+  CK(host_sum(c, c->part[0], div_parts(c), &bb));
+  *beta1 = std::sqrt(ninv * bb);
+  return std::isfinite(*beta1) ? GKB_OK : GKB_ENAN;
+}
+
+// s = M^-1 f (inner solve), y = M s, alpha = ||s||_M by the explicit product
+int gk_solve_and_norm(gkb_ctx* c, double* alpha) {
+  int its = 0;
+  CK(inner_solve_any(c, c->f, c->s, c->opt.inner_tol, &its));
+  face_op<double, kApplyDot>(c, c->op64, c->fl0, c->s, nullptr, c->y, 0.0, c->part[0], nullptr);
+  double sMs = 0.0;
+  CK(host_sum(c, c->part[0], c->fl0.nparts, &sMs));
+  *alpha = std::sqrt(sMs);
+  return (std::isfinite(*alpha) && *alpha > 0.0) ? GKB_OK : GKB_ENAN;
+}
+
+// first column: q_1 = N^-1 b / beta_1, alpha_1 M v_1 = A q_1
+int gk_first(gkb_ctx* c, GkScalars& S, double beta1) {
+  const int nc = c->g.n_cells, vbc = vec_blocks(nc);
+  hipStream_t s = c->cs;
+  S.beta = beta1;
+  k_cast<double, double><<<vbc, kBlock, 0, s>>>(nc, c->b, c->q);
+  k_axpby<<<vbc, kBlock, 0, s>>>(nc, 0.0, c->q, S.ninv / beta1, c->q);
+  grad_axpy(c, c->q, nullptr, 1.0, 0.0, c->f);  // f = A q_1
+  return gk_solve_and_norm(c, &S.alpha);
+}
+
+// next column from A^T V = N Q B^T: beta N q_{k+1} = A^T v_k - alpha_k N q_k,
+// i.e. t = N^-1 A^T v_k - alpha_k q_k, beta = ||t||_N; and from A Q = M V B:
+// alpha M v_{k+1} = A q_{k+1} - beta M v_k.  *breakdown: beta at rounding
+// level relative to alpha (both in the N-norm of t's two terms), the Krylov
+// space is exhausted
+int gk_next(gkb_ctx* c, GkScalars& S, bool* breakdown) {
+  const Grid& G = c->g;
+  const int nc = G.n_cells, vbc = vec_blocks(nc);
+  hipStream_t s = c->cs;
+  div_axpy<double>(c, G, c->v, c->q, S.ninv, -S.alpha, c->t, c->part[0], nullptr);
+  double tt = 0.0;
+  CK(host_sum(c, c->part[0], div_parts(c), &tt));
+  const double beta = std::sqrt(tt / S.ninv);
+  if (!std::isfinite(beta)) return GKB_ENAN;
+  *breakdown = beta <= 1e-13 * S.alpha;
+  if (*breakdown) return GKB_OK;
+  S.beta = beta;
+  k_cast<double, double><<<vbc, kBlock, 0, s>>>(nc, c->t, c->q);
+  k_axpby<<<vbc, kBlock, 0, s>>>(nc, 0.0, c->q, 1.0 / beta, c->q);
+  grad_axpy(c, c->q, c->Mv, 1.0, -beta, c->f);  // f = A q - beta M v
+  return gk_solve_and_norm(c, &S.alpha);
+}
+
+// Craig-variant update with the newest column, fused with the normalisation
+// of v: v = s / alpha, M v = y / alpha, zeta_k (beta_1 / alpha_1 first, then
+// -(beta_k / alpha_k) zeta_{k-1}), u += zeta v; d = (q - beta d) / alpha,
+// p -= zeta d
+void craig_update(gkb_ctx* c, GkScalars& S, bool first, double* p) {
+  const int m = c->g.m_full, nc = c->g.n_cells;
+  hipStream_t s = c->cs;
+  S.zeta = first ? S.beta / S.alpha : -(S.beta / S.alpha) * S.zeta;
+  k_gkb_faces<<<vec_blocks(m), kBlock, 0, s>>>(m, 1.0 / S.alpha, S.zeta, c->s, c->y, c->v, c->Mv,
+                                               c->u);
+  k_gkb_cells<<<vec_blocks(nc), kBlock, 0, s>>>(nc, 1.0 / S.alpha, first ? 0.0 : S.beta, S.zeta,
+                                                c->q, c->d, p);
+}
+
+// lower bound of the energy-norm error relative to the solution from the
+// newest delay+1 zeta values (Section 2.2; the non-squared ratio), -1
+// before K = delay + 1
+double lower_bound_ratio(const std::vector<double>& zs, int delay, double sum_all) {
+  const int K = (int)zs.size();
+  if (K < delay + 1) return -1.0;
+  double win = 0.0;
+  for (int j = K - delay; j <= K; ++j) win += zs[j - 1] * zs[j - 1];
+  return std::sqrt(win / sum_all);
+}
+
+// One GKB run for the right-hand sides (gv, rv); writes w = u_K + w0 and p.
+int gkb_run(gkb_ctx* c, const double* gv, const double* rv, double tol, int delay, double* w,
+            double* p, int* K_out, double* est_out) {
+  const int m = c->g.m_full, nc = c->g.n_cells, vbm = vec_blocks(m), vbc = vec_blocks(nc);
+  hipStream_t s = c->cs;
+  GkScalars S;
+  S.ninv = c->eta > 0.0 ? c->eta : 1.0;
+  double beta1 = 0.0;
+  CK(gk_transform(c, gv, rv, S.ninv, &beta1));
   k_fill<double><<<vbc, kBlock, 0, s>>>(nc, 0.0, p);
   k_fill<double><<<vbc, kBlock, 0, s>>>(nc, 0.0, c->d);
   k_fill<double><<<vbm, kBlock, 0, s>>>(m, 0.0, c->u);
   c->stats.history_len = 0;
-  if (beta1 == 0.0) {
-    k_cast<double, double><<<vbm, kBlock, 0, s>>>(m, c->w0, w);
-    HIPCK(hipStreamSynchronize(s));
-    if (K_out) *K_out = 0;
-    if (est_out) *est_out = 0.0;
-    c->stats.error_estimate = 0.0;
-    return GKB_OK;
-  }
-  // q_1 = N^-1 b / beta_1
-  k_cast<double, double><<<vbc, kBlock, 0, s>>>(nc, c->b, c->q);
-  k_axpby<<<vbc, kBlock, 0, s>>>(nc, 0.0, c->q, ninv / beta1, c->q);
   std::vector<double> zs;
-  double zeta = 0.0, alpha = 0.0, beta = 0.0, sum_all = 0.0, est = 1.0;
+  double est = 1.0, sum_all = 0.0;
   int status = GKB_MAXIT;
-  for (int K = 0; K < c->opt.maxit; ++K) {
-    if (K == 0) {
-      grad_axpy(c, c->q, nullptr, 1.0, 0.0, c->f);  // f = A q_1
-    } else {
-      // t = N^-1 A^T v - alpha q ; beta = ||t||_N
-      div_axpy<double>(c, G, c->v, c->q, ninv, -alpha, c->t, c->part[0], nullptr);
-      double tt = 0.0;
-      CK(host_sum(c, c->part[0], cell_parts(G), &tt));
-      beta = std::sqrt(tt / ninv);
-      if (!std::isfinite(beta)) return GKB_ENAN;
-      if (beta <= 1e-13 * alpha) {  // breakdown: Krylov space exhausted
+  if (beta1 == 0.0) {  // b = 0: w0 is the solution
+    est = 0.0;
+    status = GKB_OK;
+  } else {
+    CK(gk_first(c, S, beta1));
+    for (;;) {
+      craig_update(c, S, zs.empty(), p);
+      zs.push_back(S.zeta);
+      sum_all += S.zeta * S.zeta;
+      const int K = (int)zs.size();
+      const double e = lower_bound_ratio(zs, delay, sum_all);
+      if (e >= 0.0) est = e;
+      if (K <= 512) {
+        c->stats.zeta[K - 1] = S.zeta;
+        c->stats.estimate[K - 1] = e;
+        c->stats.history_len = K;
+      }
+      if (e >= 0.0 && tol > 0.0 && e <= tol) {
+        status = GKB_OK;
+        break;
+      }
+      if (K >= c->opt.maxit) break;
+      bool breakdown = false;
+      CK(gk_next(c, S, &breakdown));
+      if (breakdown) {
         est = 0.0;
         status = GKB_OK;
         break;
       }
-      k_cast<double, double><<<vbc, kBlock, 0, s>>>(nc, c->t, c->q);
-      k_axpby<<<vbc, kBlock, 0, s>>>(nc, 0.0, c->q, 1.0 / beta, c->q);
-      grad_axpy(c, c->q, c->Mv, 1.0, -beta, c->f);  // f = A q - beta M v
-    }
-    CK(inner_solve_any(c, c->f, c->s, itol, &its));
-    // y = M s, alpha = sqrt(s . M s)
-    face_op<double, kApplyDot>(c, c->op64, c->fl0, c->s, nullptr, c->y, 0.0, c->part[0], nullptr);
-    double sMs = 0.0;
-    CK(host_sum(c, c->part[0], c->fl0.nparts, &sMs));
-    alpha = std::sqrt(sMs);
-    if (!std::isfinite(alpha) || alpha == 0.0) return GKB_ENAN;
-    zeta = (K == 0) ? beta1 / alpha : -(beta / alpha) * zeta;
-    k_gkb_faces<<<vbm, kBlock, 0, s>>>(m, 1.0 / alpha, zeta, c->s, c->y, c->v, c->Mv, c->u);
-    k_gkb_cells<<<vbc, kBlock, 0, s>>>(nc, 1.0 / alpha, K == 0 ? 0.0 : beta, zeta, c->q, c->d, p);
-    zs.push_back(zeta);
-    sum_all += zeta * zeta;
-    const int Kn = K + 1;
-    double e_now = -1.0;
-    if (Kn >= delay + 1) {
-      double win = 0.0;
-      for (int j = Kn - delay; j <= Kn; ++j) win += zs[j - 1] * zs[j - 1];
-      est = std::sqrt(win / sum_all);
-      e_now = est;
-    }
-    if (Kn <= 512) {
-      c->stats.zeta[Kn - 1] = zeta;
-      c->stats.estimate[Kn - 1] = e_now;
-      c->stats.history_len = Kn;
-    }
-    if (e_now >= 0.0 && tol > 0.0 && est <= tol) {
-      status = GKB_OK;
-      break;
     }
   }
   // w = u + w0 (non-unknown faces are zero in both)
@@ -647,32 +847,155 @@ int gkb_run(gkb_ctx* c, const double* gv, const double* rv, double tol, int dela
   return status;
 }
 
+// FP64 saddle residual res = [g - W w - A p; r - A^T w] and its norms.  On
+// an assembled system with central scaling the iteration works in the
+// scaled space; user_space = true takes the user's unscaled operators (the
+// public gkb_residual), false the iteration's.
 int residual_impl(gkb_ctx* c, const double* gv, const double* rv, const double* w, const double* p,
-                  double* res_w, double* res_r, double* norms) {
+                  double* res_w, double* res_r, double* norms, bool user_space = false) {
   const Grid& G = c->g;
-  Op<double> opW = c->op64;
-  opW.eta = 0.0;
-  const FaceLaunch& fl = c->fl0;
   hipStream_t s = c->cs;
-  const bool vm = opW.mu != nullptr;
-  if (G.dim == 2) {
-    if (vm) k_resid_w<2, true><<<fl.grid, kBlock, 0, s>>>(opW, gv, w, p, res_w, fl.kz, fl.zchunks, c->part[0], c->part[1]);
-    else k_resid_w<2, false><<<fl.grid, kBlock, 0, s>>>(opW, gv, w, p, res_w, fl.kz, fl.zchunks, c->part[0], c->part[1]);
+  int nw = 0, nr = 0;
+  if (c->csr) {
+    CsrOps<double> o = c->csr64;
+    if (user_space) o.sw = o.sp = nullptr;
+    nw = vec_blocks(o.m);
+    nr = vec_blocks(o.n);
+    k_csr_resid_w<<<nw, kBlock, 0, s>>>(o, gv, w, p, res_w, c->part[0], c->part[1]);
+    k_csr_div<double><<<nr, kBlock, 0, s>>>(o, w, rv, -1.0, 1.0, res_r ? res_r : c->t, c->part[2],
+                                            c->part[3]);
   } else {
-    if (vm) k_resid_w<3, true><<<fl.grid, kBlock, 0, s>>>(opW, gv, w, p, res_w, fl.kz, fl.zchunks, c->part[0], c->part[1]);
-    else k_resid_w<3, false><<<fl.grid, kBlock, 0, s>>>(opW, gv, w, p, res_w, fl.kz, fl.zchunks, c->part[0], c->part[1]);
+    Op<double> opW = c->op64;
+    opW.eta = 0.0;
+    const FaceLaunch& fl = c->fl0;
+    const bool vm = opW.mu != nullptr;
+    if (G.dim == 2) {
+      if (vm) k_resid_w<2, true><<<fl.grid, kBlock, 0, s>>>(opW, gv, w, p, res_w, fl.kz, fl.zchunks, c->part[0], c->part[1]);
+      else k_resid_w<2, false><<<fl.grid, kBlock, 0, s>>>(opW, gv, w, p, res_w, fl.kz, fl.zchunks, c->part[0], c->part[1]);
+    } else {
+      if (vm) k_resid_w<3, true><<<fl.grid, kBlock, 0, s>>>(opW, gv, w, p, res_w, fl.kz, fl.zchunks, c->part[0], c->part[1]);
+      else k_resid_w<3, false><<<fl.grid, kBlock, 0, s>>>(opW, gv, w, p, res_w, fl.kz, fl.zchunks, c->part[0], c->part[1]);
+    }
+    div_axpy<double>(c, G, w, rv, -1.0, 1.0, res_r ? res_r : c->t, c->part[2], c->part[3]);
+    nw = fl.gparts;
+    nr = cell_parts(G);
   }
-  div_axpy<double>(c, G, w, rv, -1.0, 1.0, res_r ? res_r : c->t, c->part[2], c->part[3]);
   double rw = 0, ggw = 0, rrr = 0, rr2 = 0;
-  CK(host_sum(c, c->part[0], fl.gparts, &rw));
-  CK(host_sum(c, c->part[1], fl.gparts, &ggw));
-  CK(host_sum(c, c->part[2], cell_parts(G), &rrr));
-  CK(host_sum(c, c->part[3], cell_parts(G), &rr2));
+  CK(host_sum(c, c->part[0], nw, &rw));
+  CK(host_sum(c, c->part[1], nw, &ggw));
+  CK(host_sum(c, c->part[2], nr, &rrr));
+  CK(host_sum(c, c->part[3], nr, &rr2));
   norms[0] = std::sqrt(rw + rrr);
   norms[1] = std::sqrt(rw);
   norms[2] = std::sqrt(rrr);
   norms[3] = std::sqrt(ggw + rr2);
   return GKB_OK;
+}
+
+// GKB as a preconditioner (Section 3 offers GKB as a solver or as a
+// preconditioner): restarted flexible GMRES on the whole saddle system
+// K [w; p] = [g; r], right preconditioned by one GKB run per step (the
+// lower-bound tolerance tol, delay and maxit of the options), modified
+// Gram-Schmidt and Givens rotations on the host in FP64, every vector
+// operation on the device.  Stops when the least-squares residual estimate,
+// or the true FP64 residual at a restart, is <= refine_tol ||[g; r]||, or
+// after max_sweeps steps (GKB_MAXIT).
+int precond_solve(gkb_ctx* c, const double* gv, const double* rv, double tol, int delay,
+                  double* w, double* p, int* K_out, double* est_out) {
+  const int m = c->g.m_full, nc = c->g.n_cells;
+  const long N = (long)m + nc;
+  const int R = c->opt.outer_restart, maxit = c->opt.max_sweeps;
+  const double rtol = c->opt.refine_tol;
+  hipStream_t s = c->cs;
+  const int vbN = vec_blocks((int)N), vbm = vec_blocks(m), vbc = vec_blocks(nc);
+  auto V = [&](int j) { return c->ov + (size_t)j * N; };
+  auto Z = [&](int j) { return c->oz + (size_t)j * N; };
+  auto pdot = [&](const double* a, const double* b, double* out) {
+    k_dot<double><<<vbN, kBlock, 0, s>>>((int)N, a, b, c->part[4]);
+    return host_sum(c, c->part[4], vbN, out);
+  };
+  std::vector<double> H((size_t)(R + 1) * R, 0.0), cs(R), sn(R), gr(R + 1), y(R);
+  k_fill<double><<<vbm, kBlock, 0, s>>>(m, 0.0, w);
+  k_fill<double><<<vbc, kBlock, 0, s>>>(nc, 0.0, p);
+  int it = 0, status = GKB_MAXIT, K = 0;
+  double est = 0.0, norms[4];
+  for (;;) {
+    // true residual r = b - K x into V_0
+    CK(residual_impl(c, gv, rv, w, p, V(0), V(0) + m, norms));
+    const double beta = norms[0], bnorm = norms[3];
+    c->stats.residual = bnorm > 0.0 ? beta / bnorm : 0.0;
+    if (!std::isfinite(beta)) return GKB_ENAN;
+    if (beta <= rtol * bnorm) {
+      status = GKB_OK;
+      break;
+    }
+    if (it >= maxit) break;
+    k_axpby<<<vbN, kBlock, 0, s>>>((int)N, 0.0, V(0), 1.0 / beta, V(0));
+    std::fill(gr.begin(), gr.end(), 0.0);
+    gr[0] = beta;
+    int k = 0;
+    bool conv = false;
+    for (int j = 0; j < R && it < maxit; ++j) {
+      // z_j = GKB(v_j): one run on the right-hand side (faces, cells) of v_j
+      const int rc = gkb_run(c, V(j), V(j) + m, tol, delay, Z(j), Z(j) + m, &K, &est);
+      c->stats.sweeps += 1;
+      if (rc < 0) return rc;
+      // w = K z_j, formed as -(0 - K z_j) by the residual kernels
+      CK(residual_impl(c, c->ozero, c->ozero + m, Z(j), Z(j) + m, V(j + 1), V(j + 1) + m,
+                       norms));
+      double* wv = V(j + 1);
+      k_axpby<<<vbN, kBlock, 0, s>>>((int)N, 0.0, wv, -1.0, wv);
+      for (int i = 0; i <= j; ++i) {
+        double hij = 0.0;
+        CK(pdot(wv, V(i), &hij));
+        H[(size_t)i * R + j] = hij;
+        k_axpby<<<vbN, kBlock, 0, s>>>((int)N, -hij, V(i), 1.0, wv);
+      }
+      double ww = 0.0;
+      CK(pdot(wv, wv, &ww));
+      const double hn = std::sqrt(ww);
+      for (int i = 0; i < j; ++i) {
+        const double a = H[(size_t)i * R + j], b = H[(size_t)(i + 1) * R + j];
+        H[(size_t)i * R + j] = cs[i] * a + sn[i] * b;
+        H[(size_t)(i + 1) * R + j] = -sn[i] * a + cs[i] * b;
+      }
+      const double a = H[(size_t)j * R + j], rr = std::sqrt(a * a + hn * hn);
+      ++it;
+      if (!std::isfinite(rr)) return GKB_ENAN;
+      if (rr == 0.0) break;  // K z_j adds nothing: restart
+      cs[j] = a / rr;
+      sn[j] = hn / rr;
+      H[(size_t)j * R + j] = rr;
+      gr[j + 1] = -sn[j] * gr[j];
+      gr[j] = cs[j] * gr[j];
+      k = j + 1;
+      if (std::fabs(gr[j + 1]) <= rtol * bnorm || hn == 0.0) {
+        conv = true;
+        break;
+      }
+      k_axpby<<<vbN, kBlock, 0, s>>>((int)N, 0.0, wv, 1.0 / hn, wv);
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double v = gr[i];
+      for (int l = i + 1; l < k; ++l) v -= H[(size_t)i * R + l] * y[l];
+      y[i] = v / H[(size_t)i * R + i];
+    }
+    for (int l = 0; l < k; ++l) {
+      k_axpby<<<vbm, kBlock, 0, s>>>(m, y[l], Z(l), 1.0, w);
+      k_axpby<<<vbc, kBlock, 0, s>>>(nc, y[l], Z(l) + m, 1.0, p);
+    }
+    if (conv) {
+      CK(residual_impl(c, gv, rv, w, p, V(0), V(0) + m, norms));
+      c->stats.residual = norms[3] > 0.0 ? norms[0] / norms[3] : 0.0;
+      status = GKB_OK;
+      break;
+    }
+  }
+  HIPCK(hipStreamSynchronize(s));
+  c->stats.outer_krylov_iterations = it;
+  if (K_out) *K_out = K;
+  if (est_out) *est_out = est;
+  return status;
 }
 
 // ------------------------------------------------------------- setup
@@ -874,7 +1197,12 @@ int build_inner(gkb_ctx* c, Inner<T>& in, const std::vector<Coef<T>>& coef) {
     lv.g = c->grids[l];
     lv.op = make_op<T>(lv.g, c->eta, coef[l], c->varmu);
     lv.omega = c->omega[l];
-    lv.fl = face_launch(lv.g, 4, c->opt.stencil);
+    if (c->csr) {
+      lv.fl = FaceLaunch{};
+      lv.fl.nparts = lv.fl.gparts = vec_blocks(lv.g.m_full);
+    } else {
+      lv.fl = face_launch(lv.g, 4, c->opt.stencil);
+    }
     const int m = lv.g.m_full;
     if (l > 0) {
       CK(c->mem.arr(&lv.b, m));
@@ -905,6 +1233,14 @@ int build_inner(gkb_ctx* c, Inner<T>& in, const std::vector<Coef<T>>& coef) {
   CK(c->mem.arr(&in.q, m));
   CK(c->mem.arr(&in.rprev, m));
   CK(c->mem.arr(&in.st, 1));
+  if (c->opt.krylov == GKB_KRYLOV_FGMRES) {
+    const int R = c->opt.fgmres_restart;
+    CK(c->mem.arr(&in.gm_V, (size_t)(R + 1) * m));
+    CK(c->mem.arr(&in.gm_Z, (size_t)R * m));
+    CK(c->mem.arr(&in.gm_fs, 1));
+    CK(c->mem.arr(&in.gm_cyc, 1));
+    CK(c->mem.arr(&in.gm_part, (size_t)(R + 1) * vec_blocks(m)));
+  }
   // Jacobi preconditioner 1/diag(M) (0 at non-unknown faces)
   CK(c->mem.arr(&in.dinv, m));
   face_op<T, kDiag>(c, in.lv[0].op, in.lv[0].fl, nullptr, nullptr, in.dinv, T(0), nullptr, nullptr);
@@ -1029,6 +1365,12 @@ int setup_impl(gkb_ctx* c, const gkb_grid* grid, const double* visc, double eta,
     CK(c->mem.arr(&c->wbest, m));
     CK(c->mem.arr(&c->pbest, nc));
   }
+  if (opt->method == GKB_METHOD_PRECOND) {
+    const size_t pair = (size_t)m + nc, R = (size_t)opt->outer_restart;
+    CK(c->mem.arr(&c->ov, (R + 1) * pair));
+    CK(c->mem.arr(&c->oz, R * pair));
+    CK(c->mem.arr(&c->ozero, pair));
+  }
   // Jacobi weights by power iteration on D^-1 M_l (FP64), omega = 1.6 / (1.05 lambda)
   c->omega.assign(L, 0.8);
   for (int l = 0; l < L - (L > 1 ? 1 : 0); ++l) {
@@ -1103,10 +1445,170 @@ int setup_impl(gkb_ctx* c, const gkb_grid* grid, const double* visc, double eta,
   if (opt->precision == GKB_MIXED) CK(build_inner<float>(c, c->in32, c->coef32));
   else CK(build_inner<double>(c, c->in64, c->coef64));
   if (opt->inner != GKB_INNER_JACOBI) CK(learned_create(c));
+  if (opt->cnn_weights) {
+    if (opt->inner != GKB_INNER_LEARNED) return GKB_EINVAL;
+    if (gkb_cnn_load(opt->cnn_weights, &c->owned_net) != GKB_OK) return GKB_EINVAL;
+    CK(gkb_attach_cnn(c, c->owned_net));
+  }
+  c->opt.cnn_weights = nullptr;  // the path is not kept
   HIPCK(hipStreamSynchronize(c->cs));
   c->stats = gkb_stats_t{};
   return GKB_OK;
 }
+
+// ----------------------------------------------------- assembled systems
+
+// checks of a host CSR matrix with `rows` rows and column indices below
+// `cols`: monotone row pointers starting at 0, columns in range, finite values
+bool csr_valid(int rows, int cols, const int* ptr, const int* col, const double* val) {
+  if (rows < 1 || cols < 1 || !ptr || !col || !val || ptr[0] != 0) return false;
+  for (int i = 0; i < rows; ++i)
+    if (ptr[i + 1] < ptr[i]) return false;
+  const long nnz = ptr[rows];
+  for (long e = 0; e < nnz; ++e)
+    if (col[e] < 0 || col[e] >= cols || !std::isfinite(val[e])) return false;
+  return true;
+}
+
+template <typename T>
+int upload_csr(gkb_ctx* c, int rows, const std::vector<int>& ptr, const std::vector<int>& col,
+               const std::vector<double>& val, CsrMat<T>* out) {
+  int *dp = nullptr, *dc = nullptr;
+  T* dv = nullptr;
+  CK(c->mem.arr(&dp, ptr.size()));
+  CK(c->mem.arr(&dc, std::max<size_t>(col.size(), 1)));
+  CK(copy_sync(c, dp, ptr.data(), ptr.size() * sizeof(int), hipMemcpyHostToDevice));
+  if (!col.empty()) CK(copy_sync(c, dc, col.data(), col.size() * sizeof(int), hipMemcpyHostToDevice));
+  CK(upload<T>(c, val.empty() ? std::vector<double>(1, 0.0) : val, &dv));
+  out->rows = rows;
+  out->ptr = dp;
+  out->col = dc;
+  out->val = dv;
+  return GKB_OK;
+}
+
+int setup_csr_impl(gkb_ctx* c, const gkb_csr* sys, double eta, int scaling, const gkb_options* opt) {
+  c->opt = *opt;
+  c->eta = eta;
+  c->csr = true;
+  c->mem.cap = opt->max_workspace_bytes;
+  c->us = static_cast<hipStream_t>(opt->hip_stream);
+  HIPCK(hipStreamCreateWithFlags(&c->cs, hipStreamNonBlocking));
+  c->mem.s = c->cs;
+  HIPCK(hipEventCreateWithFlags(&c->ev, hipEventDisableTiming));
+  const int m = sys->m, n = sys->n;
+  // the vector kernels see an m-long velocity and an n-long pressure array
+  Grid G{};
+  G.dim = 0;
+  G.pin = -1;
+  G.m_full = m;
+  G.n_cells = n;
+  G.h = 1.0;
+  c->g = G;
+  c->grids.assign(1, G);
+  c->L = 1;
+  c->coef64.resize(1);
+  c->coef32.resize(1);
+  c->omega.assign(1, 0.8);
+  // host copies: W, A and the transpose of A (counting sort by column)
+  const long nw = sys->w_rowptr[m], na = sys->a_rowptr[m];
+  std::vector<int> wp(sys->w_rowptr, sys->w_rowptr + m + 1), wc(sys->w_col, sys->w_col + nw);
+  std::vector<double> wv(sys->w_val, sys->w_val + nw);
+  std::vector<int> ap(sys->a_rowptr, sys->a_rowptr + m + 1), ac(sys->a_col, sys->a_col + na);
+  std::vector<double> av(sys->a_val, sys->a_val + na);
+  std::vector<int> tp(n + 1, 0), tc(na);
+  std::vector<double> tv(na);
+  for (long e = 0; e < na; ++e) tp[ac[e] + 1] += 1;
+  for (int k = 0; k < n; ++k) tp[k + 1] += tp[k];
+  {
+    std::vector<int> fill(tp.begin(), tp.end() - 1);
+    for (int i = 0; i < m; ++i)
+      for (int e = ap[i]; e < ap[i + 1]; ++e) {
+        const int k = ac[e];
+        tc[fill[k]] = i;
+        tv[fill[k]] = av[e];
+        fill[k] += 1;
+      }
+  }
+  // diag(W) > 0 (Jacobi, scaling) and, with scaling, R = diag(A^T D^-1 A) > 0
+  std::vector<double> dw(m, 0.0);
+  for (int i = 0; i < m; ++i)
+    for (int e = wp[i]; e < wp[i + 1]; ++e)
+      if (wc[e] == i) dw[i] += wv[e];
+  for (int i = 0; i < m; ++i)
+    if (!(dw[i] > 0.0)) return GKB_EINVAL;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 0) {
+      CK(upload_csr<double>(c, m, wp, wc, wv, &c->csr64.W));
+      CK(upload_csr<double>(c, m, ap, ac, av, &c->csr64.A));
+      CK(upload_csr<double>(c, n, tp, tc, tv, &c->csr64.AT));
+    } else {
+      CK(upload_csr<float>(c, m, wp, wc, wv, &c->csr32.W));
+      CK(upload_csr<float>(c, m, ap, ac, av, &c->csr32.A));
+      CK(upload_csr<float>(c, n, tp, tc, tv, &c->csr32.AT));
+    }
+  }
+  c->csr64.m = c->csr32.m = m;
+  c->csr64.n = c->csr32.n = n;
+  if (scaling == GKB_SCALE_CENTRAL) {
+    std::vector<double> sw(m), sp(n, 0.0);
+    for (int i = 0; i < m; ++i) sw[i] = 1.0 / std::sqrt(dw[i]);
+    for (int i = 0; i < m; ++i)
+      for (int e = ap[i]; e < ap[i + 1]; ++e) sp[ac[e]] += av[e] * av[e] / dw[i];
+    for (int k = 0; k < n; ++k) {
+      if (!(sp[k] > 0.0)) return GKB_EINVAL;  // an empty column of A
+      sp[k] = 1.0 / std::sqrt(sp[k]);
+    }
+    double *sw64, *sp64;
+    float *sw32, *sp32;
+    CK(upload<double>(c, sw, &sw64));
+    CK(upload<double>(c, sp, &sp64));
+    CK(upload<float>(c, sw, &sw32));
+    CK(upload<float>(c, sp, &sp32));
+    c->csr64.sw = sw64;
+    c->csr64.sp = sp64;
+    c->csr32.sw = sw32;
+    c->csr32.sp = sp32;
+    c->csr_scaled = true;
+    CK(c->mem.arr(&c->csr_gs, m));
+    CK(c->mem.arr(&c->csr_rs, n));
+  }
+  CK(c->mem.arr(&c->csr_t64, n));
+  CK(c->mem.arr(&c->csr_t32, n));
+  c->op64 = Op<double>{};
+  c->op64.g = G;
+  c->op64.eta = eta;
+  c->op32 = Op<float>{};
+  c->op32.g = G;
+  c->op32.eta = float(eta);
+  c->fl0 = FaceLaunch{};
+  c->fl0.nparts = c->fl0.gparts = vec_blocks(m);
+  c->maxparts = std::max(vec_blocks(m), vec_blocks(n));
+  for (int i = 0; i < kSlots; ++i) CK(c->mem.arr(&c->part[i], c->maxparts));
+  CK(c->mem.arr(&c->dscal, 8));
+  HIPCK(hipHostMalloc(reinterpret_cast<void**>(&c->hbuf), 4096, hipHostMallocDefault));
+  double** fv[] = {&c->ghat, &c->w0, &c->u, &c->v, &c->Mv, &c->s, &c->y, &c->f, &c->rw, &c->dw};
+  for (auto pp : fv) CK(c->mem.arr(pp, m));
+  double** cv[] = {&c->b, &c->q, &c->d, &c->t, &c->rr, &c->dp};
+  for (auto pp : cv) CK(c->mem.arr(pp, n));
+  if (opt->refine_tol > 0.0) {
+    CK(c->mem.arr(&c->wbest, m));
+    CK(c->mem.arr(&c->pbest, n));
+  }
+  if (opt->method == GKB_METHOD_PRECOND) {
+    const size_t pair = (size_t)m + n, R = (size_t)opt->outer_restart;
+    CK(c->mem.arr(&c->ov, (R + 1) * pair));
+    CK(c->mem.arr(&c->oz, R * pair));
+    CK(c->mem.arr(&c->ozero, pair));
+  }
+  if (opt->precision == GKB_MIXED) CK(build_inner<float>(c, c->in32, c->coef32));
+  else CK(build_inner<double>(c, c->in64, c->coef64));
+  HIPCK(hipStreamSynchronize(c->cs));
+  c->stats = gkb_stats_t{};
+  return GKB_OK;
+}
+
+int validate_options(const gkb_options* o);
 
 int validate(const gkb_grid* g, double eta, const gkb_options* o) {
   if (!g || (g->dim != 2 && g->dim != 3)) return GKB_EINVAL;
@@ -1124,12 +1626,23 @@ int validate(const gkb_grid* g, double eta, const gkb_options* o) {
   }
   if (all_nat) return GKB_EINVAL;
   if (g->pin_cell < -1 || g->pin_cell >= nc) return GKB_EINVAL;
+  return validate_options(o);
+}
+
+int validate_options(const gkb_options* o) {
   if (o->precision != GKB_FP64 && o->precision != GKB_MIXED) return GKB_EINVAL;
   if (o->inner < 0 || o->inner > 2) return GKB_EINVAL;
   if (o->nu_pre < 0 || o->nu_post < 0 || o->nu_pre + o->nu_post < 1) return GKB_EINVAL;
   if (o->inner_maxit < 1 || o->maxit < 1 || o->max_sweeps < 1) return GKB_EINVAL;
   if (o->check_every < 1 || o->stencil < 0 || o->stencil > 1) return GKB_EINVAL;
   if (o->smoother != GKB_SMOOTH_JACOBI && o->smoother != GKB_SMOOTH_HYBRID) return GKB_EINVAL;
+  if (o->krylov != GKB_KRYLOV_CG && o->krylov != GKB_KRYLOV_FGMRES) return GKB_EINVAL;
+  if (o->krylov == GKB_KRYLOV_FGMRES && o->inner == GKB_INNER_LEARNED) return GKB_EINVAL;
+  if (o->fgmres_restart < 1 || o->fgmres_restart > kMaxRestart) return GKB_EINVAL;
+  if (o->method != GKB_METHOD_SOLVER && o->method != GKB_METHOD_PRECOND) return GKB_EINVAL;
+  if (o->method == GKB_METHOD_PRECOND && !(o->refine_tol > 0.0)) return GKB_EINVAL;
+  if (o->outer_restart < 1 || o->outer_restart > kMaxOuterRestart) return GKB_EINVAL;
+  if (!std::isfinite(o->learned_min_gain)) return GKB_EINVAL;
   return GKB_OK;
 }
 
@@ -1157,6 +1670,12 @@ void gkb_default_options(gkb_options* o) {
   o->smoother = GKB_SMOOTH_JACOBI;
   o->hip_stream = nullptr;
   o->max_workspace_bytes = 0;
+  o->krylov = GKB_KRYLOV_CG;
+  o->fgmres_restart = 30;
+  o->method = GKB_METHOD_SOLVER;
+  o->outer_restart = 10;
+  o->cnn_weights = nullptr;
+  o->learned_min_gain = 0.05;
 }
 
 int gkb_setup(const gkb_grid* grid, const double* viscosity, double eta, const gkb_options* opt,
@@ -1184,9 +1703,36 @@ int gkb_setup(const gkb_grid* grid, const double* viscosity, double eta, const g
   return GKB_OK;
 }
 
+int gkb_setup_csr(const gkb_csr* sys, double eta, int scaling, const gkb_options* opt,
+                  gkb_ctx** out) {
+  if (!out) return GKB_EINVAL;
+  *out = nullptr;
+  if (!sys || !(eta >= 0.0) || !std::isfinite(eta)) return GKB_EINVAL;
+  if (scaling != GKB_SCALE_NONE && scaling != GKB_SCALE_CENTRAL) return GKB_EINVAL;
+  gkb_options o;
+  if (opt) o = *opt;
+  else gkb_default_options(&o);
+  o.inner = opt ? o.inner : GKB_INNER_JACOBI;  // the default multigrid needs a grid
+  int rc = validate_options(&o);
+  if (rc) return rc;
+  if (o.inner != GKB_INNER_JACOBI || o.cnn_weights) return GKB_EINVAL;
+  if (!csr_valid(sys->m, sys->m, sys->w_rowptr, sys->w_col, sys->w_val) ||
+      !csr_valid(sys->m, sys->n, sys->a_rowptr, sys->a_col, sys->a_val))
+    return GKB_EINVAL;
+  gkb_ctx* c = new (std::nothrow) gkb_ctx();
+  if (!c) return GKB_ENOMEM;
+  rc = setup_csr_impl(c, sys, eta, scaling, &o);
+  if (rc < 0) {
+    gkb_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return GKB_OK;
+}
+
 int gkb_solve(gkb_ctx* c, const double* g, const double* r, double tol, int delay, double* w,
               double* p, int* iterations, double* error_estimate) {
-  if (!c || !g || !r || !w || !p || delay < 0) return GKB_EINVAL;
+  if (!c || !g || !r || !w || !p || delay < 1) return GKB_EINVAL;
   auto t0 = std::chrono::steady_clock::now();
   HIPCK(hipEventRecord(c->ev, c->us));
   HIPCK(hipStreamWaitEvent(c->cs, c->ev, 0));
@@ -1198,10 +1744,23 @@ int gkb_solve(gkb_ctx* c, const double* g, const double* r, double tol, int dela
   c->stats.learned_solves = 0;
   c->stats.residual = -1.0;
   c->stats.learned_gain = -1.0;
+  c->stats.learned_fallback_reason = 0;
+  c->stats.learned_fallback_iteration = 0;
+  c->stats.outer_krylov_iterations = 0;
   learned_reset(c->learned);
+  if (c->csr_scaled) {
+    // the iteration runs on the centrally scaled system: g' = D^-1/2 g,
+    // r' = R^-1/2 r; the solution is scaled back at the end
+    k_scale<<<vec_blocks(c->g.m_full), kBlock, 0, c->cs>>>(c->g.m_full, c->csr64.sw, g, c->csr_gs);
+    k_scale<<<vec_blocks(c->g.n_cells), kBlock, 0, c->cs>>>(c->g.n_cells, c->csr64.sp, r, c->csr_rs);
+    g = c->csr_gs;
+    r = c->csr_rs;
+  }
   int K = 0, rc;
   double est = 0.0;
-  if (c->opt.refine_tol <= 0.0) {
+  if (c->opt.method == GKB_METHOD_PRECOND) {
+    rc = precond_solve(c, g, r, tol, delay, w, p, &K, &est);
+  } else if (c->opt.refine_tol <= 0.0) {
     rc = gkb_run(c, g, r, tol, delay, w, p, &K, &est);
     c->stats.sweeps = 1;
   } else {
@@ -1257,6 +1816,10 @@ int gkb_solve(gkb_ctx* c, const double* g, const double* r, double tol, int dela
       k_axpby<<<vec_blocks(nc), kBlock, 0, c->cs>>>(nc, 1.0, c->dp, 1.0, p);
     }
   }
+  if (c->csr_scaled) {
+    k_scale<<<vec_blocks(c->g.m_full), kBlock, 0, c->cs>>>(c->g.m_full, c->csr64.sw, w, w);
+    k_scale<<<vec_blocks(c->g.n_cells), kBlock, 0, c->cs>>>(c->g.n_cells, c->csr64.sp, p, p);
+  }
   HIPCK(hipStreamSynchronize(c->cs));
   c->stats.seconds_solve =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1280,6 +1843,11 @@ int gkb_sizes(const gkb_ctx* c, long* m_full, long* n_cells, long* m_unknown, lo
   const Grid& g = c->g;
   if (m_full) *m_full = g.m_full;
   if (n_cells) *n_cells = g.n_cells;
+  if (c->csr) {
+    if (m_unknown) *m_unknown = g.m_full;
+    if (n_unknown) *n_unknown = g.n_cells;
+    return GKB_OK;
+  }
   long mu = 0;
   for (int cc = 0; cc < g.dim; ++cc) {
     long plane = (long)g.ext[cc][0] * g.ext[cc][1] * g.ext[cc][2] / g.ext[cc][cc];
@@ -1313,7 +1881,10 @@ void gkb_destroy(gkb_ctx* c) {
   if (c->in32.graph) (void)hipGraphExecDestroy(c->in32.graph);
   if (c->in64.graph_fcg) (void)hipGraphExecDestroy(c->in64.graph_fcg);
   if (c->in32.graph_fcg) (void)hipGraphExecDestroy(c->in32.graph_fcg);
+  if (c->in64.graph_gm) (void)hipGraphExecDestroy(c->in64.graph_gm);
+  if (c->in32.graph_gm) (void)hipGraphExecDestroy(c->in32.graph_gm);
   if (c->learned) learned_destroy(c);
+  if (c->owned_net) gkb_cnn_destroy(c->owned_net);
   c->mem.release();
   if (c->hbuf) (void)hipHostFree(c->hbuf);
   if (c->ev) (void)hipEventDestroy(c->ev);
@@ -1400,7 +1971,7 @@ int gkb_residual(gkb_ctx* c, const double* g, const double* r, const double* w, 
   if (!c || !g || !r || !w || !p || !norms) return GKB_EINVAL;
   HIPCK(hipEventRecord(c->ev, c->us));
   HIPCK(hipStreamWaitEvent(c->cs, c->ev, 0));
-  return residual_impl(c, g, r, w, p, res_w, res_r, norms);
+  return residual_impl(c, g, r, w, p, res_w, res_r, norms, true);
 }
 
 }  // extern "C"
@@ -1463,4 +2034,3 @@ extern "C" int gkb_time_kernel(gkb_ctx* c, int kernel, int reps, double* avg_ms)
   return time_kernel_impl<double>(c, c->in64, kernel, reps, avg_ms);
 }
 
-#include "learned_impl.hpp"

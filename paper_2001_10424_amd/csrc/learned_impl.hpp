@@ -31,12 +31,6 @@ struct Learned {
 
 namespace gkb {
 
-// The network correction is kept only while the error energy its step removes
-// is at least this fraction of what the V-cycle step removes (r.V(r)): one
-// application costs about as much as a V-cycle, so a smaller gain cannot pay
-// for itself.
-constexpr double kMinGain = 0.05;
-
 // squared norm of the post-V-cycle residual from block partials
 __global__ __launch_bounds__(kFinal) void k_set_rt2(PcgState* st, const double* part, int n) {
   if (st->done || st->fallback) return;
@@ -175,12 +169,15 @@ __global__ __launch_bounds__(256) void k_fcg_xr(int n, const PcgState* __restric
 
 // choose the direction: the CNN-corrected z unless it fails the descent test
 // (r.z <= 0), the residual stagnated (no decrease over 50 iterations) or the
-// network step removes less than kMinGain of the V-cycle step's error energy;
-// then fall back to the V-cycle alone for the rest of the solve, restarting
-// CG.  first = 1 at the start of a solve.
+// network step removes less than min_gain of the V-cycle step's error energy
+// (the option learned_min_gain: one application costs about as much as a
+// V-cycle, so a much smaller gain cannot pay for itself; min_gain <= 0 turns
+// this test off); then fall back to the V-cycle alone for the rest of the
+// solve, restarting CG.  first = 1 at the start of a solve.
 __global__ __launch_bounds__(kFinal) void k_fcg_beta(PcgState* st, const double* p_rzv, int nv,
                                                      const double* p_rz, const double* p_zrp,
-                                                     const double* p_zvrp, int nu, int first) {
+                                                     const double* p_zvrp, int nu, int first,
+                                                     double min_gain) {
   if (st->done) return;
   __shared__ double sh[kFinal / 64];
   const double rzv = sum_partials(p_rzv, nv, sh);
@@ -196,7 +193,8 @@ __global__ __launch_bounds__(kFinal) void k_fcg_beta(PcgState* st, const double*
     const double ratio = rzv > 0.0 ? st->gain / rzv : 0.0;
     st->gain_sum += ratio;
     st->gain_n += 1;
-    const int reason = !(rz > 0.0) ? 1 : (st->stagnant ? 2 : (ratio < kMinGain ? 3 : 0));
+    const bool low = min_gain > 0.0 && ratio < min_gain;
+    const int reason = !(rz > 0.0) ? 1 : (st->stagnant ? 2 : (low ? 3 : 0));
     if (reason) {
       st->fallback = 1;
       st->fallbacks += 1;
@@ -384,7 +382,7 @@ void fcg_iterations(gkb_ctx* c, Inner<T>& in, int count) {
     k_pcg_check<<<1, kFinal, 0, s>>>(in.st, c->part[1], vb, nullptr, 0);
     learned_precondition<T>(c, in, in.st);
     k_fcg_beta<<<1, kFinal, 0, s>>>(in.st, c->part[2], vcycle_parts<T>(c, in), c->part[3],
-                                    c->part[4], c->part[5], nu, 0);
+                                    c->part[4], c->part[5], nu, 0, c->opt.learned_min_gain);
     k_fcg_p<T><<<vb, 256, 0, s>>>(n, in.st, in.z, zv, in.p);
   }
 }
@@ -408,7 +406,7 @@ int learned_solve(gkb_ctx* c, const double* f, double* x_out, double tol, int* i
   k_pcg_start<<<1, kFinal, 0, s>>>(in.st, c->part[3], vb, c->part[3], vb, tol, c->opt.inner_maxit);
   learned_precondition<T>(c, in, nullptr);
   k_fcg_beta<<<1, kFinal, 0, s>>>(in.st, c->part[2], vcycle_parts<T>(c, in), c->part[3], c->part[4],
-                                  c->part[5], nu, 1);
+                                  c->part[5], nu, 1, c->opt.learned_min_gain);
   k_fill<T><<<vb, kBlock, 0, s>>>(n, T(0), in.p);
   k_fcg_p<T><<<vb, 256, 0, s>>>(n, in.st, in.z, zv, in.p);
   PcgState hs;
@@ -425,9 +423,8 @@ int learned_solve(gkb_ctx* c, const double* f, double* x_out, double tol, int* i
     L->gain_n += hs.gain_n;
     c->stats.learned_gain = L->gain_n ? L->gain_sum / L->gain_n : -1.0;
     L->off = true;
-    if (std::getenv("GKB_DEBUG"))
-      std::fprintf(stderr, "learned solve declined: reason %d gain %.3e\n", hs.fb_reason,
-                   hs.gain_n ? hs.gain_sum / hs.gain_n : -1.0);
+    c->stats.learned_fallback_reason = hs.fb_reason;
+    c->stats.learned_fallback_iteration = hs.fb_it;
     return kLearnedDeclined;
   }
   const int chunk = std::max(1, c->opt.check_every);
@@ -462,17 +459,16 @@ int learned_solve(gkb_ctx* c, const double* f, double* x_out, double tol, int* i
       L->gain_n += hs.gain_n;
       c->stats.learned_gain = L->gain_n ? L->gain_sum / L->gain_n : -1.0;
       L->off = true;
-      if (std::getenv("GKB_DEBUG"))
-        std::fprintf(stderr, "learned solve abandoned at it %d (fallback at %d, reason %d)\n", hs.it,
-                     hs.fb_it, hs.fb_reason);
+      c->stats.learned_fallback_reason = hs.fb_reason;
+      c->stats.learned_fallback_iteration = hs.fb_it;
       return kLearnedDeclined;
     }
   }
   k_cast<T, double><<<vb, kBlock, 0, s>>>(n, in.x, x_out);
-  if (std::getenv("GKB_DEBUG"))
-    std::fprintf(stderr, "learned solve: it %d fallback %d at it %d reason %d theta %.3e gain %.3e\n",
-                 hs.it, hs.fallbacks, hs.fb_it, hs.fb_reason, hs.theta,
-                 hs.gain_n ? hs.gain_sum / hs.gain_n : -1.0);
+  if (hs.fallbacks > 0) {
+    c->stats.learned_fallback_reason = hs.fb_reason;
+    c->stats.learned_fallback_iteration = hs.fb_it;
+  }
   if (iters) *iters = hs.it;
   c->stats.inner_iterations += hs.it;
   c->stats.inner_solves += 1;

@@ -61,6 +61,8 @@ def test_default_options(lib):
     assert o.refine_tol == 0.0 and o.max_sweeps == 10 and o.check_every == 8
     assert o.use_graphs == 1 and o.stencil == 0 and o.smoother == 0
     assert o.hip_stream is None and o.max_workspace_bytes == 0
+    assert (o.krylov, o.fgmres_restart, o.method, o.outer_restart) == (0, 30, 0, 10)
+    assert o.cnn_weights is None and o.learned_min_gain == 0.05
 
 
 def test_error_strings(lib):
@@ -101,12 +103,20 @@ def test_setup_rejects_invalid_arguments_before_any_device_work(lib):
     o = _abi.Options()
     lib.gkb_default_options(C.byref(o))
     for field, value in (("precision", 5), ("inner", 9), ("nu_pre", -1), ("maxit", 0),
-                         ("check_every", 0), ("stencil", 3), ("smoother", 4)):
+                         ("check_every", 0), ("stencil", 3), ("smoother", 4), ("krylov", 2),
+                         ("fgmres_restart", 0), ("fgmres_restart", 65), ("method", 2),
+                         ("method", 1),  # GKB as preconditioner needs refine_tol > 0
+                         ("outer_restart", 0), ("outer_restart", 33),
+                         ("learned_min_gain", float("nan"))):
         oo = _abi.Options()
         C.memmove(C.byref(oo), C.byref(o), C.sizeof(o))
         setattr(oo, field, value)
         assert lib.gkb_setup(C.byref(_grid()), None, 1.0, C.byref(oo), C.byref(ctx)) == \
             _abi.GKB_EINVAL, field
+    oo = _abi.Options()
+    C.memmove(C.byref(oo), C.byref(o), C.sizeof(o))
+    oo.inner, oo.krylov = 2, 1  # FGMRES is not offered for the learned inner solver
+    assert lib.gkb_setup(C.byref(_grid()), None, 1.0, C.byref(oo), C.byref(ctx)) == _abi.GKB_EINVAL
     mu = (C.c_double * 512)(*([1.0] * 511 + [-1.0]))  # non-positive viscosity
     assert lib.gkb_setup(C.byref(_grid()), mu, 1.0, None, C.byref(ctx)) == _abi.GKB_EINVAL
     assert lib.gkb_setup(C.byref(_grid()), None, 1.0, None, None) == _abi.GKB_EINVAL

@@ -209,6 +209,82 @@ def test_capture_train_and_learned_solve():
         assert per["learned"] <= 1.1 * per["mg"] + 5, per
 
 
+def test_learned_fcg_with_network_on_to_convergence():
+    """Flexible CG with the network correction in every direction, run to
+    convergence: with the energy-gain test off (learned_min_gain = 0) no
+    inner solve falls back, every inner solve is a learned one, and the FP64
+    saddle residual of the answer, recomputed by the oracle, meets 1e-8.  The
+    network is trained here on pairs from MG-PCG inner solves of two other
+    forcings; the iteration counts of both preconditioners are reported."""
+    _say("learned fcg network on")
+    import torch
+    from paper_2001_10424_amd.cnn import capture_pairs
+    gk = _gk()
+    ins, tgs = [], []
+    for seed in (111, 112):
+        pr = _small_problem(seed, n=24)
+        s = _solver(gk, pr, inner="mg")
+        a, b = capture_pairs(s, _dev(pr.g), _dev(pr.r), tol=1e-4, max_pairs=24)
+        ins.append(a)
+        tgs.append(b)
+        s.close()
+    inputs, targets = torch.cat(ins).contiguous(), torch.cat(tgs).contiguous()
+    net = gk.CNN(3, (4, 8, 8, 3), seed=0)
+    net.train(inputs, targets, (24, 24, 24), crop=16, batch=8, steps=100, lr=3e-3, seed=1)
+    pr = _small_problem(9, n=24)
+    res = {}
+    for inner in ("mg", "learned"):
+        s = _solver(gk, pr, inner=inner, learned_min_gain=0.0)
+        if inner == "learned":
+            s.attach_cnn(net)
+        w, p, info = s.solve(_dev(pr.g), _dev(pr.r), tol=1e-4)
+        _, _, nr = oracle.saddle_residual(pr.grid, pr.g, pr.r, w.cpu().numpy(), p.cpu().numpy())
+        assert nr[0] <= 1e-8 * nr[3], (inner, nr[0] / nr[3])
+        res[inner] = info
+        s.close()
+    il = res["learned"]
+    print("inner iterations per solve: mg", res["mg"]["inner_iterations"] / res["mg"]["inner_solves"],
+          "learned (network on)", il["inner_iterations"] / il["inner_solves"],
+          "gain", il["learned_gain"], flush=True)
+    assert il["fallbacks"] == 0 and il["learned_fallback_reason"] == 0
+    assert il["learned_solves"] == il["inner_solves"] > 0
+    assert 0.0 < il["learned_gain"] < float("inf")
+
+
+def test_network_checkpoint_as_setup_option(tmp_path):
+    """cnn_weights: the context loads and owns the network at setup, which
+    must give bitwise the solve of the same network attached by hand; a path
+    that does not load, or a network for the wrong dimension, fails setup."""
+    _say("cnn_weights option")
+    gk = _gk()
+    net = gk.CNN(3, (4, 8, 3), seed=21)
+    path = str(tmp_path / "net.bin")
+    net.save(path)
+    pr = _small_problem(3, n=16)
+    out = []
+    for how in ("attach", "option"):
+        kw = dict(learned_min_gain=0.0)
+        if how == "option":
+            kw["cnn_weights"] = path
+        s = _solver(gk, pr, **kw)
+        if how == "attach":
+            s.attach_cnn(net)
+        w, p, info = s.solve(_dev(pr.g), _dev(pr.r), tol=1e-4)
+        out.append((w.cpu().numpy(), info["inner_iterations"], info["learned_solves"]))
+        s.close()
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][1:] == out[1][1:]
+    assert out[1][2] > 0
+    with pytest.raises(RuntimeError, match="gkb_setup"):
+        _solver(gk, pr, cnn_weights=str(tmp_path / "missing.bin"))
+    net2 = gk.CNN(2, (3, 8, 2), seed=1)
+    p2 = str(tmp_path / "net2d.bin")
+    net2.save(p2)
+    with pytest.raises(RuntimeError, match="gkb_setup"):
+        _solver(gk, pr, cnn_weights=p2)
+    with pytest.raises(RuntimeError, match="gkb_setup"):  # weights need the learned inner solver
+        _solver(gk, pr, inner="mg", cnn_weights=path)
+
+
 def test_sabotaged_network_falls_back_and_converges():
     """Sign-flipped output weights make the correction point uphill: the
     descent / progress guards switch to MG-PCG and the solve still meets the

@@ -68,6 +68,34 @@ def test_stokes3d_128_lid_bench_config(mode):
     assert p[0] == 0.0 and np.all(w[pr.grid.face_mask() == 0] == 0.0)
 
 
+def test_stokes3d_128_lid_bench_config_learned():
+    """The benchmarked value mode (FP32 inner flexible CG with V-cycle + CNN
+    correction, MG-PCG fallback), with the network trained by bench.py's own
+    recipe (pairs from forcing seed 1000, 64^3 crops): FP64 residual <= 1e-8
+    by the oracle, and the statistics say which preconditioner carried the
+    inner solves."""
+    _say("stokes3d_128_lid mixed_learned")
+    import torch
+
+    import bench  # the repository root is on sys.path (tests/conftest.py)
+    gk = _gk()
+    net, train_info = bench.train_cnn(gk, torch, P, 128)
+    pr = P.stokes_problem(3, 128, seed=0, eta=1e3, lid=True)
+    s = bench.make_solver(gk, pr, "mixed_learned", net)
+    tol, delay = bench.MODES["mixed_learned"][2], bench.MODES["mixed_learned"][4]
+    w, p, info = s.solve(_dev(pr.g), _dev(pr.r), tol=tol, delay=delay)
+    s.close()
+    w, p = w.cpu().numpy(), p.cpu().numpy()
+    _, _, nr = oracle.saddle_residual(pr.grid, pr.g, pr.r, w, p)
+    print("[case] learned_solves", info["learned_solves"], "fallbacks", info["fallbacks"],
+          "gain", info["learned_gain"], "reason", info["learned_fallback_reason"],
+          "inner", info["inner_iterations"], "train", train_info, flush=True)
+    assert nr[0] <= 1e-8 * nr[3], nr[0] / nr[3]
+    assert abs(info["residual"] - nr[0] / nr[3]) <= 1e-6 * nr[0] / nr[3] + 1e-15
+    assert info["learned_solves"] >= 1
+    assert p[0] == 0.0 and np.all(w[pr.grid.face_mask() == 0] == 0.0)
+
+
 def test_stokes3d_128_operators_full_size():
     _say("operators 128^3")
     import torch

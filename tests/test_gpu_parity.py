@@ -140,6 +140,62 @@ def test_stokes_gkb_parity(dim, n, varmu, eta):
     assert _rel(w, ref["w"]) <= 1e-10 and _rel(p, ref["p"]) <= 1e-10
 
 
+MMS_CASES = [
+    # (name, grid, eta, varmu, K, p_tol): discrete manufactured solution, r != 0.
+    # p_tol: relative pressure bound.  Where eta / h^2 makes M stiff the
+    # pressure is sensitive at the level of kappa(M) * tau_in: at eta = 1e2 on
+    # these grids the oracle's own pressure moves by 4e-10 - 6e-10 under a
+    # relative 1e-15 perturbation of g (measured on the CPU), so those cases
+    # compare p at 5e-9 and w at 1e-10 (and the zeta history to 1e-10 of
+    # zeta_1 instead of 1e-13); at eta <= 10 that movement is below 3e-11 and
+    # both are compared at 1e-10.
+    ("2d_pin_eta0", P.Grid(2, (20, 14, 1), 1 / 20, (D,) * 6, 3), 0.0, False, 9, 1e-10),
+    ("2d_pin_eta10_varmu", P.Grid(2, (18, 16, 1), 1 / 18, (D,) * 6, 0), 10.0, True, 8, 1e-10),
+    ("2d_outflow_eta10", P.Grid(2, (24, 8, 1), 1 / 8, (D, N, D, D, D, D), -1), 10.0, False, 8,
+     1e-10),
+    ("2d_pin_eta1e2_varmu", P.Grid(2, (18, 16, 1), 1 / 18, (D,) * 6, 0), 1e2, True, 8, 5e-9),
+    ("3d_pin_eta0_varmu", P.Grid(3, (8, 7, 6), 1 / 8, (D,) * 6, 11), 0.0, True, 7, 1e-10),
+    ("3d_pin_eta10", P.Grid(3, (9, 8, 8), 1 / 9, (D,) * 6, 0), 10.0, False, 7, 1e-10),
+    ("3d_pin_eta1e2", P.Grid(3, (9, 8, 8), 1 / 9, (D,) * 6, 0), 1e2, False, 7, 5e-9),
+    ("3d_natural_eta10", P.Grid(3, (8, 8, 6), 1 / 8, (D, N, D, D, N, D), -1), 10.0, True, 7,
+     1e-10),
+]
+
+
+def _mms(grid, eta, varmu, seed):
+    """Discrete manufactured solution: random (w*, p*) on the unknowns,
+    g = W w* + A p*, r = A^T w* (so r != 0), built by the oracle."""
+    mu = np.exp(np.random.default_rng(seed + 100).standard_normal(grid.n_cells)) if varmu else None
+    ws, ps = P.random_solution(grid, seed)
+    g = oracle.apply_W(grid, ws, mu) + oracle.apply_A(grid, ps)
+    r = oracle.apply_AT(grid, ws)
+    return P.Problem("mms", grid, g, r, mu, eta), ws, ps
+
+
+@pytest.mark.parametrize("name,grid,eta,varmu,K,p_tol", MMS_CASES, ids=[c[0] for c in MMS_CASES])
+def test_manufactured_rhs_gkb_parity(name, grid, eta, varmu, K, p_tol):
+    """The transformation with r != 0 (ghat = g + eta A r, b = r - A^T w0,
+    the pinned cell removed) compared element by element with the oracle:
+    fixed K steps (relative 1e-10 in w and p), then a run to the stopping
+    rule that must take the oracle's K and return the manufactured solution."""
+    _say("mms parity", name)
+    pr, ws, ps = _mms(grid, eta, varmu, 5)
+    assert np.linalg.norm(pr.r) > 0
+    w, p, info, ref = _gkb_pair(pr, 0.0, K, mu=pr.mu)
+    assert info["status"] == 1 and ref["status"] == 1 and info["iterations"] == ref["K"] == K
+    assert _rel(w, ref["w"]) <= 1e-10 and _rel(p, ref["p"]) <= p_tol
+    # the smallest zeta values carry the same sensitivity as p
+    z_atol = 1e-13 if p_tol <= 1e-10 else 1e-10
+    np.testing.assert_allclose(info["zeta"], ref["zeta"], rtol=1e-9,
+                               atol=z_atol * abs(ref["zeta"][0]))
+    w, p, info, ref = _gkb_pair(pr, 1e-10, 400, mu=pr.mu)
+    assert info["status"] == ref["status"] == 0 and info["iterations"] == ref["K"]
+    assert _rel(w, ref["w"]) <= 1e-10 and _rel(p, ref["p"]) <= p_tol
+    # p* is defined up to the pressure null space only where no cell is pinned
+    # and no side is natural; every case here fixes it
+    assert _rel(w, ws) <= 1e-7 and _rel(p, ps) <= 1e-7
+
+
 def test_zero_rhs_and_errors():
     _say("zero rhs / errors")
     torch = _torch()
@@ -152,6 +208,9 @@ def test_zero_rhs_and_errors():
     with pytest.raises(RuntimeError):
         s.solve(torch.zeros(g.m_full, dtype=torch.float64, device="cuda"),
                 torch.zeros(g.n_cells, dtype=torch.float64, device="cuda"), delay=-1)
+    with pytest.raises(RuntimeError):  # the window needs d >= 1
+        s.solve(torch.zeros(g.m_full, dtype=torch.float64, device="cuda"),
+                torch.zeros(g.n_cells, dtype=torch.float64, device="cuda"), delay=0)
     s.close()
     with pytest.raises(RuntimeError):
         gk.Solver(g, None, -1.0)
