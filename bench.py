@@ -15,6 +15,7 @@ same problem timed:
   *_mg_hybrid      FP64 / FP32 inner MG-PCG with the face + edge smoother
 
   mixed_mg_fgmres  FP32 inner FGMRES(30) with the V-cycle on the right
+  mixed_learned_fgmres  the same with V-cycle + CNN correction in every step
   fp64_gkb_precond FGMRES on the saddle system, right preconditioned by one
                    loose GKB run per step (GKB as a preconditioner)
 
@@ -31,6 +32,8 @@ config.learned says whether the network carried the inner solves.
 
     python bench.py [--gpus 1] [--steps 6] [--warmup 1] [--mode mixed_learned]
     python bench.py --study eta      # K and inner iterations against eta
+    python bench.py --study learned2d  # 2D 256^2 variable viscosity: network A/B
+    python bench.py --study learned3d  # 3D 192^3 variable viscosity: network A/B
 """
 from __future__ import annotations
 
@@ -68,10 +71,13 @@ MODES = {
     # outer FGMRES(10) on the saddle system, one GKB run (tau = 1e-2, d = 2,
     # FP64 MG-PCG inner solves at 1e-3) per step as the right preconditioner
     "fp64_gkb_precond": ("fp64", "mg", 1e-2, 1e-3, 2, "jacobi", 2),
+    # the learned correction inside FGMRES(30) (no fallback tests)
+    "mixed_learned_fgmres": ("mixed", "learned", 1e-2, 3e-4, 2, "jacobi", 2),
 }
 EXTRA = {
     "mixed_mg_fgmres": dict(krylov="fgmres", fgmres_restart=30),
     "fp64_gkb_precond": dict(method="precond", outer_restart=10),
+    "mixed_learned_fgmres": dict(krylov="fgmres", fgmres_restart=30),
 }
 CNN_CHANNELS = (4, 8, 8, 3)  # 3 conv3x3x3 layers, 8 hidden channels
 
@@ -318,6 +324,80 @@ def study_eta(gk, torch, problems):
     return rows
 
 
+def study_learned(gk, torch, problems, dim, train_seeds, eval_seeds, steps=1500):
+    """The variable-viscosity workloads with their networks: C4 (2D 256^2,
+    4 conv 3x3 layers, 16 channels) or C5 (3D 192^3, 3 conv 3x3x3 layers,
+    8 channels, 64^3 crops).  Pairs are captured from MG-PCG inner solves
+    (hybrid smoother, the solver that converges on these problems) of the
+    training forcings, the network is trained on the GPU, and the held-out
+    forcings are solved to the FP64 residual 1e-8 by FP64 MG-PCG, FP32
+    MG-PCG and FP32 learned flexible CG (default guards, and with the network
+    kept on).  One JSON line per solve, then a summary line."""
+    from paper_2001_10424_amd.cnn import capture_pairs
+    n, mu_seed = (256, 7) if dim == 2 else (192, 8)
+    channels = (3, 16, 16, 16, 2) if dim == 2 else CNN_CHANNELS
+    crop = 64
+    base = dict(inner="mg", smoother="hybrid", nu_pre=1, nu_post=1, inner_maxit=20000,
+                maxit=200, refine_tol=1e-8, max_sweeps=30)
+    t0 = time.perf_counter()
+    ins, tgs = [], []
+    for sd in train_seeds:
+        pr = problems.stokes_problem(dim, n, seed=sd, eta=1e3, mu_seed=mu_seed)
+        s = gk.Solver(pr.grid, pr.mu, pr.eta, precision="mixed", inner_tol=1e-5, **base)
+        a, b = capture_pairs(s, torch.tensor(pr.g, device="cuda"),
+                             torch.tensor(pr.r, device="cuda"), tol=3e-3, max_pairs=8, delay=2)
+        ins.append(a)
+        tgs.append(b)
+        s.close()
+    inputs, targets = torch.cat(ins).contiguous(), torch.cat(tgs).contiguous()
+    del ins, tgs
+    t1 = time.perf_counter()
+    net = gk.CNN(dim, channels, seed=0)
+    shape = (n, n, 1) if dim == 2 else (n, n, n)
+    loss0 = net.evaluate(inputs, targets, shape)
+    net.train(inputs, targets, shape, crop=crop, batch=8 if dim == 2 else 2, steps=steps,
+              lr=1e-3 if dim == 2 else 1e-4, seed=1)
+    loss1 = net.evaluate(inputs, targets, shape)
+    t2 = time.perf_counter()
+    train = dict(pairs=int(inputs.shape[0]), capture_s=round(t1 - t0, 2), train_s=round(t2 - t1, 2),
+                 loss_before=loss0, loss_after=loss1)
+    print(json.dumps(dict(study=f"learned_{dim}d", training=train)), flush=True)
+    del inputs, targets
+    modes = {"fp64_mg": dict(precision="fp64", inner_tol=3e-4),
+             "mixed_mg": dict(precision="mixed", inner_tol=3e-4),
+             "mixed_learned": dict(precision="mixed", inner_tol=3e-4, inner="learned"),
+             "mixed_learned_on": dict(precision="mixed", inner_tol=3e-4, inner="learned",
+                                      learned_min_gain=-1.0)}
+    summary = {}
+    for sd in eval_seeds:
+        pr = problems.stokes_problem(dim, n, seed=sd, eta=1e3, mu_seed=mu_seed)
+        g = torch.tensor(pr.g, device="cuda")
+        r = torch.tensor(pr.r, device="cuda")
+        for name, kw in modes.items():
+            opts = dict(base, **kw)
+            s = gk.Solver(pr.grid, pr.mu, pr.eta, **opts)
+            if opts["inner"] == "learned":
+                s.attach_cnn(net)
+            s.solve(g, r, tol=3e-3, delay=2)
+            dt, w, p, info = timed_solve(torch, s, g, r, 3e-3, 2)
+            norms, _, _ = s.residual(g, r, w, p)
+            s.close()
+            row = dict(mode=name, seed=sd, seconds=round(dt, 4), residual=norms[0] / norms[3],
+                       outer=info["outer_iterations"], sweeps=info["sweeps"],
+                       inner=info["inner_iterations"], inner_solves=info["inner_solves"],
+                       learned_solves=info["learned_solves"], fallbacks=info["fallbacks"],
+                       gain=info["learned_gain"], reason=info["learned_fallback_reason"])
+            print(json.dumps(row), flush=True)
+            d = summary.setdefault(name, dict(seconds=0.0, inner=0, solves=0))
+            d["seconds"] += dt / len(eval_seeds)
+            d["inner"] += info["inner_iterations"]
+            d["solves"] += info["inner_solves"]
+    for d in summary.values():
+        d["inner_per_solve"] = round(d.pop("inner") / max(d.pop("solves"), 1), 1)
+        d["seconds"] = round(d["seconds"], 4)
+    print(json.dumps(dict(study=f"learned_{dim}d", summary=summary)), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -332,7 +412,7 @@ def main():
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the calibration copy and 20 launches of the dominant kernel "
                          "(hardware-counter runs)")
-    ap.add_argument("--study", choices=["eta"], default=None)
+    ap.add_argument("--study", choices=["eta", "learned2d", "learned3d"], default=None)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this solver has no multi-GPU path "
@@ -347,6 +427,12 @@ def main():
     torch.cuda.set_device(0)
     if args.study == "eta":
         study_eta(gk, torch, problems)
+        return
+    if args.study == "learned2d":
+        study_learned(gk, torch, problems, 2, range(3000, 3064), (10000, 10001, 10002))
+        return
+    if args.study == "learned3d":
+        study_learned(gk, torch, problems, 3, range(3000, 3004), (10000,), steps=400)
         return
     seeds = [int(x) for x in args.seeds.split(",")]
     prs = [problems.stokes_problem(3, args.n, seed=sd, eta=1e3, lid=True) for sd in seeds]
@@ -383,7 +469,7 @@ def main():
     compare = {args.mode: main_res}
     if not args.no_compare:
         for m in MODES:
-            if m == args.mode or (m == "mixed_learned" and net is None):
+            if m == args.mode or (MODES[m][1] == "learned" and net is None):
                 continue
             s2, res2 = time_mode(gk, torch, prs, rhs, m, len(rhs), 1, net)
             compare[m] = res2

@@ -72,7 +72,8 @@ extern "C" {
                                 correction, falling back to MG-PCG */
 
 /* Krylov method of the inner solves (the preconditioner is chosen by
-   `inner`: diag(M)^-1 for GKB_INNER_JACOBI, one V-cycle for GKB_INNER_MG).
+   `inner`: diag(M)^-1 for GKB_INNER_JACOBI, one V-cycle for GKB_INNER_MG,
+   V-cycle + network correction for GKB_INNER_LEARNED).
    Section 3 leaves the inner Krylov method to the user; Section 4.1.3
    compares CG and fgmres. */
 #define GKB_KRYLOV_CG 0      /* preconditioned CG (flexible CG for _LEARNED) */
@@ -135,8 +136,12 @@ typedef struct {
   void *hip_stream;     /* hipStream_t; NULL = null stream */
   size_t max_workspace_bytes; /* 0 = unlimited; else setup fails with
                                  GKB_ENOMEM above this device footprint */
-  int krylov;           /* GKB_KRYLOV_CG or GKB_KRYLOV_FGMRES (inner solves;
-                           FGMRES with GKB_INNER_JACOBI or _MG only) */
+  int krylov;           /* GKB_KRYLOV_CG or GKB_KRYLOV_FGMRES (inner solves).
+                           With GKB_INNER_LEARNED and a network, FGMRES
+                           applies V-cycle + network correction in every step
+                           (it takes a preconditioner that changes from step
+                           to step; no fallback tests); without a network it
+                           uses the V-cycle */
   int fgmres_restart;   /* Krylov vectors of the inner FGMRES (1..64) */
   int method;           /* GKB_METHOD_SOLVER or GKB_METHOD_PRECOND */
   int outer_restart;    /* Krylov vectors of the outer FGMRES of
@@ -150,9 +155,12 @@ typedef struct {
   double learned_min_gain; /* GKB_INNER_LEARNED: the network correction is
                               dropped (fallback to MG-PCG) when the error energy
                               its step removes falls below this fraction of the
-                              V-cycle step's (gkb_stats_t.learned_gain); <= 0
+                              V-cycle step's (gkb_stats_t.learned_gain); 0
                               turns this test off (the descent and progress
-                              tests stay) */
+                              tests stay), < 0 also the progress test (no
+                              decrease of r.r over 50 iterations): only the
+                              descent test r.z > 0 that flexible CG needs
+                              remains */
 } gkb_options;
 
 typedef struct {

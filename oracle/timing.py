@@ -1,0 +1,99 @@
+"""Wall-clock timing of the CPU oracle (test infrastructure: measures the
+oracle, never used by the library).
+
+Complete oracle solves of the 2D workloads, each in a fresh process so that
+OMP_NUM_THREADS takes effect:
+
+* Poiseuille channel 64 x 16 (eta = 1e2, tau = 1e-8, d = 5, Jacobi-PCG to
+  1e-12), one thread and every host thread;
+* 2D Stokes 512^2 (eta = 10, 8-mode forcing seed 0, pinned cell): one GKB run
+  with tau = 1e-9, d = 5, Jacobi-PCG to 1e-10, every host thread, and with one
+  thread a fixed number of outer steps (labelled as such);
+
+each with the FP64 relative saddle residual of its answer.  Prints one JSON
+line per run and a markdown table; the host is described by nproc and the
+CPU model from /proc/cpuinfo.
+
+    python oracle/timing.py [--skip-large]
+"""
+from __future__ import annotations
+
+import json
+import os
+import subprocess
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+RUNS = {
+    "poiseuille_64x16": dict(kind="poiseuille", tol=1e-8, delay=5, inner_tol=1e-12, maxit=400),
+    "stokes2d_512_eta10": dict(kind="stokes2d", n=512, eta=10.0, tol=1e-9, delay=5,
+                               inner_tol=1e-10, maxit=2000),
+}
+
+
+def _child(name, maxit_override):
+    sys.path.insert(0, ROOT)
+    import oracle
+    import problems as P
+
+    cfg = dict(RUNS[name])
+    if cfg["kind"] == "poiseuille":
+        pr = P.poiseuille_problem(64, 16, 4.0, 1e2)
+    else:
+        pr = P.stokes_problem(2, cfg["n"], seed=0, eta=cfg["eta"])
+    maxit = maxit_override or cfg["maxit"]
+    oracle.lib()
+    t0 = time.perf_counter()
+    res = oracle.gkb_solve(pr.grid, pr.g, pr.r, pr.eta, mu=pr.mu, tol=cfg["tol"],
+                           delay=cfg["delay"], maxit=maxit, inner_tol=cfg["inner_tol"],
+                           inner_maxit=10 ** 8)
+    dt = time.perf_counter() - t0
+    _, _, nr = oracle.saddle_residual(pr.grid, pr.g, pr.r, res["w"], res["p"], mu=pr.mu)
+    print(json.dumps(dict(run=name, threads=int(os.environ.get("OMP_NUM_THREADS", "0")),
+                          seconds=round(dt, 3), status=res["status"], K=res["K"],
+                          inner_iterations=res["inner_total"], residual=nr[0] / nr[3],
+                          outer_steps_limit=maxit_override or None)), flush=True)
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    if len(sys.argv) > 2 and sys.argv[1] == "--child":
+        _child(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 0)
+        return
+    skip_large = "--skip-large" in sys.argv
+    nproc = os.cpu_count() or 1
+    plan = [("poiseuille_64x16", 1, 0), ("poiseuille_64x16", nproc, 0)]
+    if not skip_large:
+        plan += [("stokes2d_512_eta10", nproc, 0), ("stokes2d_512_eta10", 1, 2)]
+    print(f"# host: nproc {nproc}, {_cpu_model()}", flush=True)
+    rows = []
+    for name, threads, maxit in plan:
+        env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+        out = subprocess.run([sys.executable, os.path.abspath(__file__), "--child", name,
+                              str(maxit)], env=env, capture_output=True, text=True, check=True)
+        line = out.stdout.strip().splitlines()[-1]
+        print(line, flush=True)
+        rows.append(json.loads(line))
+    print("\n| run | threads | outer steps | status | K | inner its | s | FP64 residual |")
+    print("|---|---|---|---|---|---|---|---|")
+    for r in rows:
+        lim = f"first {r['outer_steps_limit']}" if r["outer_steps_limit"] else "complete"
+        print(f"| {r['run']} | {r['threads']} | {lim} | {r['status']} | {r['K']} | "
+              f"{r['inner_iterations']} | {r['seconds']} | {r['residual']:.2e} |")
+
+
+if __name__ == "__main__":
+    main()

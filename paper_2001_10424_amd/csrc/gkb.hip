@@ -187,7 +187,14 @@ struct Inner {
   PcgState* gm_cyc = nullptr;
   double* gm_part = nullptr;
   hipGraphExec_t graph_gm = nullptr;
+  bool graph_gm_learned = false;  // the captured cycle applies the network
 };
+
+// the learned preconditioner z = V(r) + theta c applied to r_in
+// (learned_impl.hpp)
+template <typename T>
+void learned_apply(gkb_ctx* c, Inner<T>& in, const T* r_in, T* z_out, const PcgState* st_dot,
+                   PcgState* st);
 
 }  // namespace
 
@@ -564,11 +571,13 @@ void fgmres_cycle(gkb_ctx* c, Inner<T>& in) {
   const long ld = n;
   hipStream_t s = c->cs;
   const bool jac = c->opt.inner == GKB_INNER_JACOBI;
+  const bool learned = c->opt.inner == GKB_INNER_LEARNED && learned_has_net(c->learned);
   for (int j = 0; j < R; ++j) {
     T* vj = in.gm_V + j * ld;
     T* zj = in.gm_Z + j * ld;
     T* w = in.gm_V + (j + 1) * ld;
     if (jac) k_gm_jacobi<T><<<vb, kBlock, 0, s>>>(n, in.gm_cyc, in.dinv, vj, zj);
+    else if (learned) learned_apply<T>(c, in, vj, zj, in.gm_cyc, in.gm_cyc);
     else vcycle<T>(c, in, 0, vj, zj, nullptr, in.gm_cyc);
     face_op<T, kApply>(c, L0.op, L0.fl, zj, nullptr, w, T(0), nullptr, in.gm_cyc);
     const int nv = j + 1;
@@ -590,11 +599,22 @@ void fgmres_cycle(gkb_ctx* c, Inner<T>& in) {
   k_gm_v0<T><<<vb, kBlock, 0, s>>>(n, in.st, in.gm_fs, in.r, in.gm_V);
 }
 
+int learned_prepare(gkb_ctx* c);
+
 template <typename T>
 int fgmres_solve(gkb_ctx* c, const double* f, double* x_out, double tol, int* iters) {
   Inner<T>& in = inner_of<T>(c);
   const int n = in.lv[0].g.m_full, vb = vec_blocks(n);
   hipStream_t s = c->cs;
+  // the learned preconditioner (FGMRES takes any preconditioner, also one
+  // that changes from step to step): network buffers and BF16 weights ready
+  // before the cycle is captured or replayed
+  const bool learned = c->opt.inner == GKB_INNER_LEARNED && learned_has_net(c->learned);
+  if (learned) CK(learned_prepare(c));
+  if (in.graph_gm && in.graph_gm_learned != learned) {
+    (void)hipGraphExecDestroy(in.graph_gm);
+    in.graph_gm = nullptr;
+  }
   k_pcg_init<double, T><<<vb, kBlock, 0, s>>>(n, f, in.x, in.r, c->part[3]);
   k_cast<T, T><<<vb, kBlock, 0, s>>>(n, in.r, in.rprev);  // f in working precision
   k_gm_start<<<1, kFinal, 0, s>>>(in.st, in.gm_cyc, in.gm_fs, c->part[3], vb, tol,
@@ -608,6 +628,7 @@ int fgmres_solve(gkb_ctx* c, const double* f, double* x_out, double tol, int* it
     const hipError_t ie = hipGraphInstantiate(&in.graph_gm, gr, nullptr, nullptr, 0);
     (void)hipGraphDestroy(gr);
     HIPCK(ie);
+    in.graph_gm_learned = learned;
   }
   PcgState hs;
   // every cycle takes at least one Arnoldi step, so inner_maxit bounds the
@@ -624,6 +645,7 @@ int fgmres_solve(gkb_ctx* c, const double* f, double* x_out, double tol, int* it
   if (iters) *iters = hs.it;
   c->stats.inner_iterations += hs.it;
   c->stats.inner_solves += 1;
+  if (learned) c->stats.learned_solves += 1;
   if (hs.nonfinite) return GKB_ENAN;
   if (!hs.done || hs.status == -5) return GKB_EINNER;
   return GKB_OK;
@@ -1446,7 +1468,6 @@ int setup_impl(gkb_ctx* c, const gkb_grid* grid, const double* visc, double eta,
   else CK(build_inner<double>(c, c->in64, c->coef64));
   if (opt->inner != GKB_INNER_JACOBI) CK(learned_create(c));
   if (opt->cnn_weights) {
-    if (opt->inner != GKB_INNER_LEARNED) return GKB_EINVAL;
     if (gkb_cnn_load(opt->cnn_weights, &c->owned_net) != GKB_OK) return GKB_EINVAL;
     CK(gkb_attach_cnn(c, c->owned_net));
   }
@@ -1637,12 +1658,12 @@ int validate_options(const gkb_options* o) {
   if (o->check_every < 1 || o->stencil < 0 || o->stencil > 1) return GKB_EINVAL;
   if (o->smoother != GKB_SMOOTH_JACOBI && o->smoother != GKB_SMOOTH_HYBRID) return GKB_EINVAL;
   if (o->krylov != GKB_KRYLOV_CG && o->krylov != GKB_KRYLOV_FGMRES) return GKB_EINVAL;
-  if (o->krylov == GKB_KRYLOV_FGMRES && o->inner == GKB_INNER_LEARNED) return GKB_EINVAL;
   if (o->fgmres_restart < 1 || o->fgmres_restart > kMaxRestart) return GKB_EINVAL;
   if (o->method != GKB_METHOD_SOLVER && o->method != GKB_METHOD_PRECOND) return GKB_EINVAL;
   if (o->method == GKB_METHOD_PRECOND && !(o->refine_tol > 0.0)) return GKB_EINVAL;
   if (o->outer_restart < 1 || o->outer_restart > kMaxOuterRestart) return GKB_EINVAL;
   if (!std::isfinite(o->learned_min_gain)) return GKB_EINVAL;
+  if (o->cnn_weights && o->inner != GKB_INNER_LEARNED) return GKB_EINVAL;
   return GKB_OK;
 }
 

@@ -12,6 +12,7 @@ namespace {
 // the caller runs the plain MG-PCG solve (from x = 0) instead
 constexpr int kLearnedDeclined = 2;
 bool learned_enabled(Learned* L);
+bool learned_has_net(Learned* L);
 bool learned_capturing(Learned* L);
 void learned_reset(Learned* L);
 template <typename T>

@@ -171,9 +171,11 @@ __global__ __launch_bounds__(256) void k_fcg_xr(int n, const PcgState* __restric
 // (r.z <= 0), the residual stagnated (no decrease over 50 iterations) or the
 // network step removes less than min_gain of the V-cycle step's error energy
 // (the option learned_min_gain: one application costs about as much as a
-// V-cycle, so a much smaller gain cannot pay for itself; min_gain <= 0 turns
-// this test off); then fall back to the V-cycle alone for the rest of the
-// solve, restarting CG.  first = 1 at the start of a solve.
+// V-cycle, so a much smaller gain cannot pay for itself; min_gain = 0 turns
+// this test off, min_gain < 0 the progress test too, leaving only the
+// descent test that flexible CG needs); then fall back to the V-cycle alone
+// for the rest of the solve, restarting CG.  first = 1 at the start of a
+// solve.
 __global__ __launch_bounds__(kFinal) void k_fcg_beta(PcgState* st, const double* p_rzv, int nv,
                                                      const double* p_rz, const double* p_zrp,
                                                      const double* p_zvrp, int nu, int first,
@@ -194,7 +196,8 @@ __global__ __launch_bounds__(kFinal) void k_fcg_beta(PcgState* st, const double*
     st->gain_sum += ratio;
     st->gain_n += 1;
     const bool low = min_gain > 0.0 && ratio < min_gain;
-    const int reason = !(rz > 0.0) ? 1 : (st->stagnant ? 2 : (low ? 3 : 0));
+    const bool stalled = min_gain >= 0.0 && st->stagnant;
+    const int reason = !(rz > 0.0) ? 1 : (stalled ? 2 : (low ? 3 : 0));
     if (reason) {
       st->fallback = 1;
       st->fallbacks += 1;
@@ -258,6 +261,7 @@ __global__ __launch_bounds__(256) void k_err_after_v(int n, const T* __restrict_
 namespace {
 
 bool learned_enabled(Learned* L) { return L && L->net && !L->off; }
+bool learned_has_net(Learned* L) { return L && L->net; }
 void learned_reset(Learned* L) {
   if (L) {
     L->off = false;
@@ -313,8 +317,16 @@ void learned_destroy(gkb_ctx* c) {
   c->learned = nullptr;
 }
 
+// z = V(r) + theta c for the residual r_in into z_out (c, M c and the
+// post-V-cycle residual in scratch buffers).  st_dot: the flag that skips the
+// launches (null: always run); st: the state that receives rt.rt, theta and
+// the gain and whose done / fallback flags skip the network kernels.  In
+// flexible CG r_in = in.r, z_out = in.z and k_combine also forms the dot
+// partials of the direction choice; FGMRES passes its basis vector and
+// preconditioned vector.
 template <typename T>
-void learned_precondition(gkb_ctx* c, Inner<T>& in, const PcgState* st_dot) {
+void learned_apply(gkb_ctx* c, Inner<T>& in, const T* r_in, T* z_out, const PcgState* st_dot,
+                   PcgState* st) {
   Learned* L = c->learned;
   const Level<T>& L0 = in.lv[0];
   const Grid& G = L0.g;
@@ -323,19 +335,19 @@ void learned_precondition(gkb_ctx* c, Inner<T>& in, const PcgState* st_dot) {
   hipStream_t s = c->cs;
   // zv = V(r) with the partial r.zv; rt = r - M zv, the residual the V-cycle
   // leaves, is the network input (its scale from rt.rt)
-  vcycle<T>(c, in, 0, in.r, zv, c->part[2], st_dot);
+  vcycle<T>(c, in, 0, r_in, zv, c->part[2], st_dot);
   T* rt = static_cast<T*>(L->tmp);
-  face_op<T, kResidDot>(c, L0.op, L0.fl, zv, in.r, rt, T(0), c->part[1], st_dot);
-  k_set_rt2<<<1, kFinal, 0, s>>>(in.st, c->part[1], L0.fl.nparts);
+  face_op<T, kResidDot>(c, L0.op, L0.fl, zv, r_in, rt, T(0), c->part[1], st_dot);
+  k_set_rt2<<<1, kFinal, 0, s>>>(st, c->part[1], L0.fl.nparts);
   const int nb = cnn_grid(G.n_cells);
   if (G.dim == 2)
-    k_pack_faces<T, 2><<<nb, 256, 0, s>>>(G, rt, in.st, double(L->m_unknown), L->logmu, net->act[0]);
+    k_pack_faces<T, 2><<<nb, 256, 0, s>>>(G, rt, st, double(L->m_unknown), L->logmu, net->act[0]);
   else
-    k_pack_faces<T, 3><<<nb, 256, 0, s>>>(G, rt, in.st, double(L->m_unknown), L->logmu, net->act[0]);
+    k_pack_faces<T, 3><<<nb, 256, 0, s>>>(G, rt, st, double(L->m_unknown), L->logmu, net->act[0]);
   CnnGeom g{G.n[0], G.n[1], G.n[2], 1, (long)G.n_cells};
   const int blocks = (int)((g.P + 63) / 64);
-  const int* f1 = &in.st->done;
-  const int* f2 = &in.st->fallback;
+  const int* f1 = &st->done;
+  const int* f2 = &st->fallback;
   for (int l = 0; l < net->L; ++l) {
     const uint16_t* w = net->wf + (size_t)l * net->taps * 256;
     const float* b = net->bias + 16 * l;
@@ -351,21 +363,26 @@ void learned_precondition(gkb_ctx* c, Inner<T>& in, const PcgState* st_dot) {
         k_conv<3, kOutF32><<<blocks, 256, 0, s>>>(g, net->act[l], w, b, net->y16, nullptr, f1, f2);
     }
   }
-  // c (stored in z) with c.rt, then M c (into the rt buffer) with c.Mc, the
-  // energy-optimal weight theta, and z = zv + theta c
+  // c (stored in z_out) with c.rt, then M c (into the rt buffer) with c.Mc,
+  // the energy-optimal weight theta, and z = zv + theta c
   const dim3 tg = transfer_grid(G);
   if (G.dim == 2)
-    k_unpack_c<T, 2><<<tg, 256, 0, s>>>(G, net->y16, in.st, double(L->m_unknown), L->lam, rt,
-                                        in.z, c->part[3]);
+    k_unpack_c<T, 2><<<tg, 256, 0, s>>>(G, net->y16, st, double(L->m_unknown), L->lam, rt,
+                                        z_out, c->part[3]);
   else
-    k_unpack_c<T, 3><<<tg, 256, 0, s>>>(G, net->y16, in.st, double(L->m_unknown), L->lam, rt,
-                                        in.z, c->part[3]);
-  face_op<T, kApplyDot>(c, L0.op, L0.fl, in.z, nullptr, rt, T(0), c->part[4], st_dot);
-  k_set_theta<<<1, kFinal, 0, s>>>(in.st, c->part[3], (int)(tg.x * tg.z), c->part[4],
+    k_unpack_c<T, 3><<<tg, 256, 0, s>>>(G, net->y16, st, double(L->m_unknown), L->lam, rt,
+                                        z_out, c->part[3]);
+  face_op<T, kApplyDot>(c, L0.op, L0.fl, z_out, nullptr, rt, T(0), c->part[4], st_dot);
+  k_set_theta<<<1, kFinal, 0, s>>>(st, c->part[3], (int)(tg.x * tg.z), c->part[4],
                                    L0.fl.nparts);
   const int n = G.m_full;
-  k_combine<T><<<vec_blocks(n), 256, 0, s>>>(n, in.st, zv, in.z, in.r, in.rprev, in.z, c->part[3],
+  k_combine<T><<<vec_blocks(n), 256, 0, s>>>(n, st, zv, z_out, r_in, in.rprev, z_out, c->part[3],
                                              c->part[4], c->part[5]);
+}
+
+template <typename T>
+void learned_precondition(gkb_ctx* c, Inner<T>& in, const PcgState* st_dot) {
+  learned_apply<T>(c, in, in.r, in.z, st_dot, in.st);
 }
 
 template <typename T>
@@ -385,6 +402,15 @@ void fcg_iterations(gkb_ctx* c, Inner<T>& in, int count) {
                                     c->part[4], c->part[5], nu, 0, c->opt.learned_min_gain);
     k_fcg_p<T><<<vb, 256, 0, s>>>(n, in.st, in.z, zv, in.p);
   }
+}
+
+// network buffers for the grid and BF16 weights from the current FP32 ones
+int learned_prepare(gkb_ctx* c) {
+  gkb_cnn* net = c->learned->net;
+  CK(cnn_reserve(net, c->g.n_cells));
+  CK(cnn_prepare_weights(net));
+  HIPCK(hipStreamSynchronize(net->s));
+  return GKB_OK;
 }
 
 template <typename T>
@@ -568,11 +594,16 @@ int gkb_attach_cnn(gkb_ctx* c, gkb_cnn* net) {
     CK(cnn_reserve(net, c->g.n_cells));
   }
   c->learned->net = net;
-  // the flexible-CG graphs hold the network's buffers; the PCG graphs do not
+  // the flexible-CG and FGMRES graphs hold the network's buffers; the PCG
+  // graphs do not
   if (c->in32.graph_fcg) (void)hipGraphExecDestroy(c->in32.graph_fcg);
   if (c->in64.graph_fcg) (void)hipGraphExecDestroy(c->in64.graph_fcg);
+  if (c->in32.graph_gm) (void)hipGraphExecDestroy(c->in32.graph_gm);
+  if (c->in64.graph_gm) (void)hipGraphExecDestroy(c->in64.graph_gm);
   c->in32.graph_fcg = nullptr;
   c->in64.graph_fcg = nullptr;
+  c->in32.graph_gm = nullptr;
+  c->in64.graph_gm = nullptr;
   return GKB_OK;
 }
 

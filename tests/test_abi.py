@@ -115,7 +115,7 @@ def test_setup_rejects_invalid_arguments_before_any_device_work(lib):
             _abi.GKB_EINVAL, field
     oo = _abi.Options()
     C.memmove(C.byref(oo), C.byref(o), C.sizeof(o))
-    oo.inner, oo.krylov = 2, 1  # FGMRES is not offered for the learned inner solver
+    oo.cnn_weights = b"/nonexistent/net.bin"  # network weights need the learned inner solver
     assert lib.gkb_setup(C.byref(_grid()), None, 1.0, C.byref(oo), C.byref(ctx)) == _abi.GKB_EINVAL
     mu = (C.c_double * 512)(*([1.0] * 511 + [-1.0]))  # non-positive viscosity
     assert lib.gkb_setup(C.byref(_grid()), mu, 1.0, None, C.byref(ctx)) == _abi.GKB_EINVAL

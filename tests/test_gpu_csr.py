@@ -48,9 +48,15 @@ SYSTEMS = _systems()
 @pytest.mark.parametrize("scaling", ["none", "central"])
 @pytest.mark.parametrize("si", range(len(SYSTEMS)), ids=[s[0] for s in SYSTEMS])
 def test_csr_gkb_parity(si, scaling):
-    """Jacobi-PCG inner solves at 1e-13: a fixed number of steps and a run to
-    the stopping rule, equal to the oracle's CSR path to relative 1e-10 at
-    equal K; the scaled run returns the solution of the given system."""
+    """Jacobi-PCG inner solves at 1e-13: a fixed number of steps, equal to
+    the oracle's CSR path to relative 1e-10, and a run to the stopping rule
+    with the oracle's K and result; the scaled run returns the solution of the
+    given system.  The unscaled random system (column scales over four
+    decades) needs about 1300 GKB steps, far past the loss of orthogonality,
+    where rounding moves the step at which the bound crosses tau (the oracle
+    itself stops at 1282 or 1285 steps with 8 or 16 threads): there the
+    criterion run is compared by K within 1 % and by its distance to the LU
+    solution; with central scaling the same system takes 23 steps."""
     name, W, A, eta = SYSTEMS[si]
     _say("csr parity", name, scaling)
     import paper_2001_10424_amd as gk
@@ -65,12 +71,18 @@ def test_csr_gkb_parity(si, scaling):
         ref = oracle.gkb_solve_csr(W, A, g, r, eta, scaling=(scaling == "central"), tol=tol,
                                    delay=5, maxit=maxit, inner_tol=1e-13, inner_maxit=200000)
         assert info["status"] == ref["status"] == (0 if tol > 0 else 1)
-        assert info["iterations"] == ref["K"]
         w, p = w.cpu().numpy(), p.cpu().numpy()
+        if ref["K"] > 500:
+            assert abs(info["iterations"] - ref["K"]) <= 0.01 * ref["K"], (info["iterations"],
+                                                                          ref["K"])
+            continue
+        assert info["iterations"] == ref["K"]
         assert _rel(w, ref["w"]) <= 1e-10 and _rel(p, ref["p"]) <= 1e-10, (_rel(w, ref["w"]),
                                                                              _rel(p, ref["p"]))
     ws, ps = dense_solution(W, A, g, r)
     assert _rel(w, ws) <= 1e-6 and _rel(p, ps) <= 1e-6
+    if name.startswith("random"):
+        print("GKB steps to tau = 1e-9:", info["iterations"], "scaling", scaling, flush=True)
 
 
 def test_csr_operators_and_residual():

@@ -104,19 +104,22 @@ def test_tiled_matches_generic(name, grid, eta, varmu, smoother):
 
 
 def test_vcycle_laplacian_convergence_factor():
-    """eta = 0 (M = W, the vector Laplacian): MG-PCG converges in few
-    iterations, independent of the grid size (textbook multigrid)."""
+    """eta = 0 (M = W, the vector Laplacian): the mean residual reduction per
+    MG-PCG iteration, (1e-8)^(1 / iterations), is a textbook V(2,2) factor
+    (<= 0.2) and does not grow with the grid."""
     _say("laplacian mg")
     gk = _gk()
     its = []
-    for n in (16, 32, 64):
+    for n in (16, 32, 64, 128):
         g = P.Grid(3, (n, n, n), 1 / n, (D,) * 6, 0)
         s = gk.Solver(g, None, 0.0, inner="mg")
         f = _dev(P.random_vector(g, 3))
         _, it = s.inner_solve(f, 1e-8)
         its.append(it)
         s.close()
-    assert max(its) <= 20 and its[-1] <= its[0] + 4, its
+    rho = [1e-8 ** (1.0 / k) for k in its]
+    print("[case] iterations", its, "factors", [round(r, 3) for r in rho], flush=True)
+    assert max(rho) <= 0.2 and its[-1] <= its[0] + 2, (its, rho)
 
 
 @pytest.mark.parametrize("smoother", ["jacobi", "hybrid"])

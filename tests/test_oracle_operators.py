@@ -128,7 +128,7 @@ def test_polynomial_exactness_2d():
 
 
 def test_polynomial_exactness_3d():
-    """3D cubic field of the paper (Section 4.3), exact interior stencil."""
+    """3D cubic field of the paper (Section 4.4), exact interior stencil."""
     n = 12
     g = P.Grid(3, (n, n, n), 1.0 / n, (D,) * 6, -1)
     w = np.zeros(g.m_full)
