@@ -413,6 +413,11 @@ def main():
                     help="only the calibration copy and 20 launches of the dominant kernel "
                          "(hardware-counter runs)")
     ap.add_argument("--study", choices=["eta", "learned2d", "learned3d"], default=None)
+    ap.add_argument("--varvisc-profile", action="store_true",
+                    help="profiling run of the 3D variable-viscosity workload (192^3, "
+                         "log-normal mu, contrast 1e3): one FP32 hybrid-smoother MG-GKB solve "
+                         "to 1e-8, then the finest-grid sweep alone (20 launches); prints "
+                         "the kernel's HIP-event time")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this solver has no multi-GPU path "
@@ -433,6 +438,29 @@ def main():
         return
     if args.study == "learned3d":
         study_learned(gk, torch, problems, 3, range(3000, 3004), (10000,), steps=400)
+        return
+    if args.varvisc_profile:
+        pr = problems.stokes_problem(3, 192, seed=10000, eta=1e3, mu_seed=8)
+        g = torch.tensor(pr.g, device="cuda")
+        r = torch.tensor(pr.r, device="cuda")
+        s = gk.Solver(pr.grid, pr.mu, pr.eta, precision="mixed", inner="mg", smoother="hybrid",
+                      nu_pre=1, nu_post=1, inner_tol=3e-4, inner_maxit=20000, maxit=200,
+                      refine_tol=1e-8, max_sweeps=30)
+        s.solve(g, r, tol=3e-3, delay=2)
+        dt, w, p, info = timed_solve(torch, s, g, r, 3e-3, 2)
+        norms, _, _ = s.residual(g, r, w, p)
+        ms = s.time_kernel("smooth", 20)
+        # plain sweep y = x + omega D^-1 (b - M x): x, b read, y written, and the
+        # cell viscosity and three edge-viscosity arrays read (FP32)
+        m_full, nc = s.m_full, pr.grid.n_cells
+        edges = sum((pr.grid.n[0] + (b != 0)) * (pr.grid.n[1] + (b != 1)) *
+                    (pr.grid.n[2] + (b != 2)) for b in range(3))
+        nbytes = (3 * m_full + nc + edges) * 4
+        print(json.dumps({"workload": "varvisc3d_192", "solve_s": round(dt, 4),
+                          "residual": norms[0] / norms[3], "inner": info["inner_iterations"],
+                          "smooth_avg_ms": ms, "bytes_per_launch": nbytes,
+                          "achieved_GBs": round(nbytes / (ms * 1e-3) / 1e9, 1)}))
+        s.close()
         return
     seeds = [int(x) for x in args.seeds.split(",")]
     prs = [problems.stokes_problem(3, args.n, seed=sd, eta=1e3, lid=True) for sd in seeds]
