@@ -79,7 +79,10 @@ extern "C" {
 #define GKB_KRYLOV_CG 0      /* preconditioned CG (flexible CG for _LEARNED) */
 #define GKB_KRYLOV_FGMRES 1  /* restarted flexible GMRES, right preconditioned,
                                 restart fgmres_restart; stops on the same
-                                relative residual as CG */
+                                relative residual as CG: in FP64 the residual
+                                recomputed at each restart, in FP32 (mixed)
+                                also the least-squares estimate of the last
+                                cycle, as CG stops on its recursive residual */
 
 /* how gkb_solve uses GKB (Section 3: GKB as a solver or as a preconditioner) */
 #define GKB_METHOD_SOLVER 0  /* GKB runs (with defect correction when
@@ -100,6 +103,21 @@ extern "C" {
                                 Jacobi leaves when eta >> mu); face then edge
                                 before, edge then face after the coarse
                                 correction, so the V-cycle stays symmetric */
+
+/* multigrid transfers of the V-cycle.  Both prolongations are linear along
+   a face's normal; across it (tangential directions):
+   DIV     constant over the two fine cells: a coarse divergence-free field
+           maps to a divergence-free fine field, which a V-cycle on
+           M = W + eta A A^T needs when eta >> mu (the grad-div term's near
+           null space is the divergence-free space);
+   SMOOTH  linear between coarse row centres (mirror ghosts at the sides):
+           second order, the textbook pair for the vector Laplacian (eta
+           small against mu), with a grid-independent V-cycle;
+   AUTO    SMOOTH when eta <= 100 mu_ref, else DIV, with mu_ref the geometric
+           mean of the cell viscosity (1 without one) */
+#define GKB_TRANSFER_AUTO 0
+#define GKB_TRANSFER_DIV 1
+#define GKB_TRANSFER_SMOOTH 2
 
 typedef struct {
   int dim;       /* 2 or 3 */
@@ -161,6 +179,8 @@ typedef struct {
                               decrease of r.r over 50 iterations): only the
                               descent test r.z > 0 that flexible CG needs
                               remains */
+  int mg_transfer;      /* GKB_TRANSFER_AUTO / _DIV / _SMOOTH: the multigrid
+                           prolongation (restriction: its transpose / 2^d) */
 } gkb_options;
 
 typedef struct {
@@ -199,6 +219,8 @@ typedef struct {
   int learned_fallback_iteration; /* inner iteration of that fallback */
   int outer_krylov_iterations;    /* GKB_METHOD_PRECOND: outer FGMRES
                                      iterations (= GKB runs) of the last solve */
+  int mg_transfer;                /* transfer pair in use (GKB_TRANSFER_DIV or
+                                     GKB_TRANSFER_SMOOTH) */
 } gkb_stats_t;
 
 typedef struct gkb_ctx gkb_ctx;
@@ -207,7 +229,7 @@ typedef struct gkb_ctx gkb_ctx;
    smoother, inner_tol 1e-10, inner_maxit 10000, maxit 500, refine_tol 0,
    max_sweeps 10, check_every 8, graphs on, null stream, CG inner solves,
    fgmres_restart 30, GKB as the solver, outer_restart 10, no network file,
-   learned_min_gain 0.05. */
+   learned_min_gain 0.05, mg_transfer GKB_TRANSFER_AUTO. */
 void gkb_default_options(gkb_options *opt);
 
 /* Create a context for one grid, viscosity field and eta (the paper's nu).

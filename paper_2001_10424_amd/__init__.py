@@ -48,7 +48,8 @@ class Solver:
       smoother ("jacobi" | "hybrid"), krylov ("cg" | "fgmres"), fgmres_restart,
       method ("solver" | "precond": GKB as the solver or as the preconditioner
       of an outer FGMRES), outer_restart, cnn_weights (checkpoint path loaded at
-      setup), learned_min_gain, mg_levels, nu_pre, nu_post, inner_tol,
+      setup), learned_min_gain, mg_transfer ("auto" | "div" | "smooth"),
+      mg_levels, nu_pre, nu_post, inner_tol,
       inner_maxit, maxit, refine_tol, max_sweeps, check_every, use_graphs,
       stencil, max_workspace_bytes.
     """
@@ -88,6 +89,8 @@ class Solver:
                 v = _abi.KRYLOV.get(v, v)
             elif k == "method":
                 v = _abi.METHODS.get(v, v)
+            elif k == "mg_transfer":
+                v = _abi.TRANSFERS.get(v, v)
             elif k == "cnn_weights":
                 v = None if v is None else str(v).encode()
             if not hasattr(opt, k):
@@ -165,7 +168,8 @@ class Solver:
                     learned_gain=st.learned_gain,
                     learned_fallback_reason=st.learned_fallback_reason,
                     learned_fallback_iteration=st.learned_fallback_iteration,
-                    outer_krylov_iterations=st.outer_krylov_iterations)
+                    outer_krylov_iterations=st.outer_krylov_iterations,
+                    mg_transfer={1: "div", 2: "smooth"}.get(st.mg_transfer, "none"))
 
     def apply(self, op, x, precision="fp64"):
         """y = op(x) for op in W, A, AT, M, diag (gkb_apply)."""

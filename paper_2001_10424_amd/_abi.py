@@ -18,6 +18,7 @@ KERNELS = {"smooth": 0, "apply": 1, "resid": 2, "smooth_prolong": 3, "smooth_zer
 SMOOTHERS = {"jacobi": 0, "hybrid": 1}
 KRYLOV = {"cg": 0, "fgmres": 1}
 METHODS = {"solver": 0, "precond": 1}
+TRANSFERS = {"auto": 0, "div": 1, "smooth": 2}
 SCALE_NONE, SCALE_CENTRAL = 0, 1
 
 class Grid(C.Structure):
@@ -42,7 +43,7 @@ class Options(C.Structure):
                 ("hip_stream", C.c_void_p), ("max_workspace_bytes", C.c_size_t),
                 ("krylov", C.c_int), ("fgmres_restart", C.c_int), ("method", C.c_int),
                 ("outer_restart", C.c_int), ("cnn_weights", C.c_char_p),
-                ("learned_min_gain", C.c_double)]
+                ("learned_min_gain", C.c_double), ("mg_transfer", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -55,7 +56,7 @@ class Stats(C.Structure):
                 ("mg_levels", C.c_int), ("omega", C.c_double * 16),
                 ("omega_edge", C.c_double * 16), ("learned_gain", C.c_double),
                 ("learned_fallback_reason", C.c_int), ("learned_fallback_iteration", C.c_int),
-                ("outer_krylov_iterations", C.c_int)]
+                ("outer_krylov_iterations", C.c_int), ("mg_transfer", C.c_int)]
 
 
 _lib = None

@@ -209,13 +209,19 @@ __global__ void k_gm_cycle_end(PcgState* st, const FgmState* fs) {
 
 // start of a cycle from r (partials of r.r): beta = ||r||, g = beta e_1.
 // first = 1 also initialises the solve's state (rr0 = f.f, tolerance,
-// iteration cap).  At a restart the true residual decides: done when it
-// meets the tolerance (also where the least-squares estimate of the last
+// iteration cap).  At a restart the recomputed residual decides: done when
+// it meets the tolerance (also where the least-squares estimate of the last
 // cycle already did: near rounding level the two part), else done with
-// status -5 once the iteration cap is reached
+// status -5 once the iteration cap is reached.  accept_estimate = 1 (FP32
+// inner solves) also ends the solve when the last cycle's least-squares
+// estimate met the tolerance: that estimate plays the part of CG's
+// recursive residual, while f - M x formed in FP32 has a rounding floor
+// of about eps_32 |M| |x| / |f|, which on grad-div dominated M (eta >> mu)
+// lies above the loose inner tolerances of the mixed-precision solver; the
+// FP64 defect correction around the inner solves removes what is left
 __global__ __launch_bounds__(kFinal) void k_gm_start(PcgState* st, PcgState* cyc, FgmState* fs,
                                                      const double* part_rr, int nrr, double tol,
-                                                     int maxit, int first) {
+                                                     int maxit, int first, int accept_estimate) {
   if (!first && st->done) return;
   __shared__ double sh[kFinal / 64];
   const double rr = sum_partials(part_rr, nrr, sh);
@@ -232,7 +238,7 @@ __global__ __launch_bounds__(kFinal) void k_gm_start(PcgState* st, PcgState* cyc
     st->nonfinite = 1;
     st->status = -4;
     st->done = 1;
-  } else if (rr <= st->tol2 * st->rr0) {
+  } else if (rr <= st->tol2 * st->rr0 || (accept_estimate && fs->conv)) {
     st->done = 1;
     st->status = 0;
   } else if (st->it >= st->maxit) {

@@ -206,6 +206,7 @@ struct gkb_ctx {
   hipStream_t cs = nullptr;  // own non-blocking stream
   hipEvent_t ev = nullptr;
   bool varmu = false;
+  bool smooth_transfer = false;  // SMOOTH multigrid transfers (else DIV)
   Alloc mem;
   int L = 1;
   std::vector<Grid> grids;
@@ -428,10 +429,14 @@ void vcycle(gkb_ctx* c, Inner<T>& in, int l, const T* b, T* x, double* dot_parti
   const T omc = T(Lc.omega);
   const T* rsrc = cur ? L.rb : b;
   if (cur) face_op<T, kResid>(c, L.op, L.fl, cur, b, L.rb, T(0), nullptr, st);
-  if (L.g.dim == 2)
-    k_restrict<T, 2><<<tg, kBlock, 0, s>>>(L.g, Lc.g, rsrc, Lc.b, st, Lc.dinv, omc, x0c);
-  else
-    k_restrict<T, 3><<<tg, kBlock, 0, s>>>(L.g, Lc.g, rsrc, Lc.b, st, Lc.dinv, omc, x0c);
+  const bool sm = c->smooth_transfer;
+  if (L.g.dim == 2) {
+    if (sm) k_restrict<T, 2, true><<<tg, kBlock, 0, s>>>(L.g, Lc.g, rsrc, Lc.b, st, Lc.dinv, omc, x0c);
+    else k_restrict<T, 2, false><<<tg, kBlock, 0, s>>>(L.g, Lc.g, rsrc, Lc.b, st, Lc.dinv, omc, x0c);
+  } else {
+    if (sm) k_restrict<T, 3, true><<<tg, kBlock, 0, s>>>(L.g, Lc.g, rsrc, Lc.b, st, Lc.dinv, omc, x0c);
+    else k_restrict<T, 3, false><<<tg, kBlock, 0, s>>>(L.g, Lc.g, rsrc, Lc.b, st, Lc.dinv, omc, x0c);
+  }
   vcycle<T>(c, in, l + 1, Lc.b, Lc.x, nullptr, st, x0c != nullptr);
   // prolongate into the current iterate (or into a zeroed x when no pre-smoothing)
   T* it = const_cast<T*>(cur);
@@ -440,9 +445,9 @@ void vcycle(gkb_ctx* c, Inner<T>& in, int l, const T* b, T* x, double* dot_parti
     k_fill<T><<<vec_blocks(L.g.m_full), kBlock, 0, s>>>(L.g.m_full, T(0), it);
   }
   // the coarse-grid correction is added while the first post-smoothing sweep
-  // stages its input (tiled grids, weighted-Jacobi smoother, that sweep not
-  // the one that forms the dot product)
-  const bool pro = cur && n2 >= 1 && !hybrid && L.fl.tiled && !(n2 == 1 && dot_partial);
+  // stages its input (tiled grids, weighted-Jacobi smoother, divergence-
+  // compatible transfers, that sweep not the one that forms the dot product)
+  const bool pro = cur && n2 >= 1 && !hybrid && !sm && L.fl.tiled && !(n2 == 1 && dot_partial);
   int i0 = 0;
   if (pro) {
     ++k;
@@ -452,8 +457,13 @@ void vcycle(gkb_ctx* c, Inner<T>& in, int l, const T* b, T* x, double* dot_parti
     i0 = 1;
   } else {
     const dim3 fg = transfer_grid(L.g);
-    if (L.g.dim == 2) k_prolong_add<T, 2><<<fg, kBlock, 0, s>>>(L.g, Lc.g, Lc.x, it, st);
-    else k_prolong_add<T, 3><<<fg, kBlock, 0, s>>>(L.g, Lc.g, Lc.x, it, st);
+    if (L.g.dim == 2) {
+      if (sm) k_prolong_add<T, 2, true><<<fg, kBlock, 0, s>>>(L.g, Lc.g, Lc.x, it, st);
+      else k_prolong_add<T, 2, false><<<fg, kBlock, 0, s>>>(L.g, Lc.g, Lc.x, it, st);
+    } else {
+      if (sm) k_prolong_add<T, 3, true><<<fg, kBlock, 0, s>>>(L.g, Lc.g, Lc.x, it, st);
+      else k_prolong_add<T, 3, false><<<fg, kBlock, 0, s>>>(L.g, Lc.g, Lc.x, it, st);
+    }
     cur = it;
   }
   for (int i = i0; i < n2; ++i) {
@@ -595,7 +605,8 @@ void fgmres_cycle(gkb_ctx* c, Inner<T>& in) {
   k_gm_update_x<T><<<vb, kBlock, 0, s>>>(n, in.st, in.gm_fs, in.gm_Z, ld, in.x);
   k_gm_cycle_end<<<1, 64, 0, s>>>(in.st, in.gm_fs);
   face_op<T, kResidDot>(c, L0.op, L0.fl, in.x, in.rprev, in.r, T(0), c->part[1], in.st);
-  k_gm_start<<<1, kFinal, 0, s>>>(in.st, in.gm_cyc, in.gm_fs, c->part[1], L0.fl.nparts, 0.0, 0, 0);
+  k_gm_start<<<1, kFinal, 0, s>>>(in.st, in.gm_cyc, in.gm_fs, c->part[1], L0.fl.nparts, 0.0, 0, 0,
+                                  sizeof(T) == 4 ? 1 : 0);
   k_gm_v0<T><<<vb, kBlock, 0, s>>>(n, in.st, in.gm_fs, in.r, in.gm_V);
 }
 
@@ -618,7 +629,7 @@ int fgmres_solve(gkb_ctx* c, const double* f, double* x_out, double tol, int* it
   k_pcg_init<double, T><<<vb, kBlock, 0, s>>>(n, f, in.x, in.r, c->part[3]);
   k_cast<T, T><<<vb, kBlock, 0, s>>>(n, in.r, in.rprev);  // f in working precision
   k_gm_start<<<1, kFinal, 0, s>>>(in.st, in.gm_cyc, in.gm_fs, c->part[3], vb, tol,
-                                  c->opt.inner_maxit, 1);
+                                  c->opt.inner_maxit, 1, 0);
   k_gm_v0<T><<<vb, kBlock, 0, s>>>(n, in.st, in.gm_fs, in.r, in.gm_V);
   if (c->opt.use_graphs && !in.graph_gm) {
     hipGraph_t gr;
@@ -1287,6 +1298,18 @@ int setup_impl(gkb_ctx* c, const gkb_grid* grid, const double* visc, double eta,
   int n[3] = {grid->n[0], grid->n[1], grid->dim == 3 ? grid->n[2] : 1};
   c->g = make_grid(grid->dim, n, grid->h, grid->bc, grid->pin_cell);
   c->varmu = visc != nullptr;
+  {
+    // AUTO transfers: SMOOTH while the grad-div term is weak against the
+    // viscous one, eta <= 100 mu_ref (mu_ref: geometric mean viscosity)
+    double mu_ref = 1.0;
+    if (visc) {
+      double sl = 0.0;
+      for (int i = 0; i < c->g.n_cells; ++i) sl += std::log(visc[i]);
+      mu_ref = std::exp(sl / c->g.n_cells);
+    }
+    c->smooth_transfer = opt->mg_transfer == GKB_TRANSFER_SMOOTH ||
+                         (opt->mg_transfer == GKB_TRANSFER_AUTO && eta <= 100.0 * mu_ref);
+  }
   // levels
   int L = opt->mg_levels;
   if (opt->inner == GKB_INNER_JACOBI) L = 1;
@@ -1663,6 +1686,7 @@ int validate_options(const gkb_options* o) {
   if (o->method == GKB_METHOD_PRECOND && !(o->refine_tol > 0.0)) return GKB_EINVAL;
   if (o->outer_restart < 1 || o->outer_restart > kMaxOuterRestart) return GKB_EINVAL;
   if (!std::isfinite(o->learned_min_gain)) return GKB_EINVAL;
+  if (o->mg_transfer < GKB_TRANSFER_AUTO || o->mg_transfer > GKB_TRANSFER_SMOOTH) return GKB_EINVAL;
   if (o->cnn_weights && o->inner != GKB_INNER_LEARNED) return GKB_EINVAL;
   return GKB_OK;
 }
@@ -1697,6 +1721,7 @@ void gkb_default_options(gkb_options* o) {
   o->outer_restart = 10;
   o->cnn_weights = nullptr;
   o->learned_min_gain = 0.05;
+  o->mg_transfer = GKB_TRANSFER_AUTO;
 }
 
 int gkb_setup(const gkb_grid* grid, const double* viscosity, double eta, const gkb_options* opt,
@@ -1856,6 +1881,7 @@ int gkb_stats(const gkb_ctx* c, gkb_stats_t* out) {
   out->mg_levels = c->L;
   for (int l = 0; l < c->L && l < 16; ++l) out->omega[l] = c->omega[l];
   for (int l = 0; l < (int)c->omega_e.size() && l < 16; ++l) out->omega_edge[l] = c->omega_e[l];
+  out->mg_transfer = c->smooth_transfer ? GKB_TRANSFER_SMOOTH : GKB_TRANSFER_DIV;
   return GKB_OK;
 }
 

@@ -38,12 +38,15 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return s;
 }
 
-// Sum of n partials in a fixed order (one block of kFinal threads).
-__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int n, double* sh) {
+// Sum of n partials in a fixed order (one block of kFinal threads): each
+// thread's strided share, then the block sum.
+__device__ __forceinline__ double thread_partials(const double* __restrict__ part, int n) {
   double v = 0.0;
   for (int i = threadIdx.x; i < n; i += kFinal) v += part[i];
-  double s = block_sum<kFinal>(v, sh);
-  return s;  // valid in thread 0
+  return v;
+}
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int n, double* sh) {
+  return block_sum<kFinal>(thread_partials(part, n), sh);  // valid in thread 0
 }
 
 __global__ __launch_bounds__(kFinal) void k_sum_partials(const double* part, int n, double* out) {
@@ -406,10 +409,14 @@ __global__ __launch_bounds__(kFinal) void k_pcg_start(PcgState* st, const double
   }
 }
 
+// The one-block scalar kernels below read the done flag together with the
+// partials (the flag is tested once both loads are in flight).
 __global__ __launch_bounds__(kFinal) void k_pcg_alpha(PcgState* st, const double* part_pq, int n) {
-  if (st->done) return;
+  const int done = st->done;
+  const double v = thread_partials(part_pq, n);
+  if (done) return;
   __shared__ double sh[kFinal / 64];
-  const double pq = sum_partials(part_pq, n, sh);
+  const double pq = block_sum<kFinal>(v, sh);
   if (threadIdx.x == 0) {
     st->pq = pq;
     const double a = st->rz / pq;
@@ -433,12 +440,16 @@ __global__ __launch_bounds__(kBlock) void k_pcg_xr(int n, const PcgState* __rest
                                                    const T* __restrict__ dinv, T* __restrict__ z,
                                                    double* __restrict__ part_rr,
                                                    double* __restrict__ part_rz) {
-  if (st->done) return;
+  // the flag and alpha are tested / used once this thread's first loads are
+  // in flight
+  const int done = st->done;
   const T a = T(st->alpha);
   double s = 0.0, t = 0.0;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    x[i] += a * p[i];
-    const T ri = r[i] - a * q[i];
+    const T xi = x[i], pi = p[i], r0 = r[i], qi = q[i];
+    if (done) break;
+    x[i] = xi + a * pi;
+    const T ri = r0 - a * qi;
     r[i] = ri;
     s += double(ri) * double(ri);
     if (dinv) {
@@ -447,6 +458,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_xr(int n, const PcgState* __rest
       t += double(ri) * double(zi);
     }
   }
+  if (done) return;  // uniform: every thread of the block leaves
   __shared__ double sh[kBlock / 64];
   double v = block_sum<kBlock>(s, sh);
   if (threadIdx.x == 0) part_rr[blockIdx.x] = v;
@@ -460,13 +472,16 @@ __global__ __launch_bounds__(kBlock) void k_pcg_xr(int n, const PcgState* __rest
 // convergence test on r.r; with part_rz also the CG beta (Jacobi path)
 __global__ __launch_bounds__(kFinal) void k_pcg_check(PcgState* st, const double* part_rr, int nrr,
                                                       const double* part_rz, int nrz) {
-  if (st->done) return;
+  const int done = st->done;
+  const double vrr = thread_partials(part_rr, nrr);
+  const double vrz = part_rz ? thread_partials(part_rz, nrz) : 0.0;
+  if (done) return;
   __shared__ double sh[kFinal / 64];
-  const double rr = sum_partials(part_rr, nrr, sh);
+  const double rr = block_sum<kFinal>(vrr, sh);
   double rz = 0.0;
   if (part_rz) {
     __syncthreads();
-    rz = sum_partials(part_rz, nrz, sh);
+    rz = block_sum<kFinal>(vrz, sh);
   }
   if (threadIdx.x == 0) {
     st->rr = rr;
@@ -497,9 +512,11 @@ __global__ __launch_bounds__(kFinal) void k_pcg_check(PcgState* st, const double
 
 // preconditioned path: rz_new from the partials of the last V-cycle kernel
 __global__ __launch_bounds__(kFinal) void k_pcg_beta(PcgState* st, const double* part_rz, int n) {
-  if (st->done) return;
+  const int done = st->done;
+  const double v = thread_partials(part_rz, n);
+  if (done) return;
   __shared__ double sh[kFinal / 64];
-  const double rz = sum_partials(part_rz, n, sh);
+  const double rz = block_sum<kFinal>(v, sh);
   if (threadIdx.x == 0) {
     st->beta = rz / st->rz;
     st->rz = rz;
@@ -518,71 +535,113 @@ __global__ __launch_bounds__(kBlock) void k_pcg_p(int n, const PcgState* __restr
 
 // ------------------------------------------------------------ multigrid
 
+// Tangential weights of the two transfer pairs.  DIV (divergence
+// compatible): a fine face takes the value of the coarse face whose cell
+// pair covers it, constant across the two fine cells in each tangential
+// direction.  SMOOTH: linear in each tangential direction between the
+// centres of the coarse rows, 3/4 from the row that covers the fine row and
+// 1/4 from the next row on the fine row's side; beyond a side that next row
+// is a mirror ghost, -1 times the covering row at a DIRICHLET wall (zero
+// tangential velocity on the wall) and +1 times it at a NATURAL side.
+// Weight of coarse row T in the value of fine row t along a tangential axis
+// with nc coarse rows and side types lo / hi:
+__device__ __forceinline__ double tan_weight(int t, int T, int nc, int lo, int hi) {
+  const int Tc = t >> 1, Tn = (t & 1) ? Tc + 1 : Tc - 1;
+  double w = 0.0;
+  if (Tc == T) {
+    w = 0.75;
+    if (Tn < 0) w += lo == kDir ? -0.25 : 0.25;
+    if (Tn >= nc) w += hi == kDir ? -0.25 : 0.25;
+  } else if (Tn == T) {
+    w = 0.25;
+  }
+  return w;
+}
+
 // Restriction of face residuals, full weighting: coarse face = (1/2^d) *
 // sum over the fine faces it covers, normal neighbours weighted 1/2
-// (transpose of the prolongation below divided by 2^d).
+// (transpose of the prolongation below divided by 2^d); SMOOTH also takes
+// the fine rows next to the covered ones in each tangential direction, with
+// the transposed weights.
 // x0c (optional): the coarse level's first smoothing sweep from a zero
 // guess, x0c = omega_c dinv_c bc, written in the same pass
-template <typename T, int DIM, int C>
+template <typename T, int DIM, int C, bool SM>
 __device__ __forceinline__ void restrict_face(const Grid& Gf, const Grid& Gc,
                                               const T* __restrict__ rf, T* __restrict__ bc,
                                               const T* __restrict__ dinv_c, T omega_c,
-                                              T* __restrict__ x0c, int idx, int k) {
+                                              T* __restrict__ x0c, int idx, int k, int done) {
   const int e0 = Gc.ext[C][0], e1 = Gc.ext[C][1];
   if (idx >= e0 * e1 || k >= Gc.ext[C][2]) return;
   const int j = idx / e0, i = idx - j * e0;
   const int P[3] = {i, j, k};
   const int f = fidx<C>(Gc, i, j, k);
   if (!unk<C>(Gc, P[C])) {
+    if (done) return;
     bc[f] = T(0);
     if (x0c) x0c[f] = T(0);
     return;
   }
   T acc = T(0);
   const int nfC = Gf.n[C];
+  const int A1 = (C + 1) % DIM;
+  const int A2 = (C + 2) % 3;
+  // fine rows per tangential axis: the two covered ones (DIV), with one
+  // more on each side (SMOOTH)
+  constexpr int kT = SM ? 4 : 2, kT0 = SM ? -1 : 0;
 #pragma unroll
   for (int dn = -1; dn <= 1; ++dn) {
     const int fn = 2 * P[C] + dn;
     if (fn < 0 || fn > nfC) continue;
     const T wn = dn == 0 ? T(1) : T(0.5);
 #pragma unroll
-    for (int t1 = 0; t1 < 2; ++t1)
+    for (int t1 = 0; t1 < kT; ++t1)
 #pragma unroll
-      for (int t2 = 0; t2 < (DIM == 3 ? 2 : 1); ++t2) {
+      for (int t2 = 0; t2 < (DIM == 3 ? kT : 1); ++t2) {
         int Q[3];
         Q[C] = fn;
-        const int A1 = (C + 1) % DIM;
-        const int A2 = (C + 2) % 3;
-        Q[A1] = 2 * P[A1] + t1;
-        if (DIM == 3) Q[A2] = 2 * P[A2] + t2;
+        Q[A1] = 2 * P[A1] + kT0 + t1;
+        if (DIM == 3) Q[A2] = 2 * P[A2] + kT0 + t2;
         else Q[2] = 0;
-        acc += wn * ldm<C>(Gf, rf, Q[0], Q[1], Q[2]);
+        T w = wn;
+        if (SM) {
+          if (Q[A1] < 0 || Q[A1] >= Gf.n[A1]) continue;
+          w *= T(tan_weight(Q[A1], P[A1], Gc.n[A1], Gc.bc[2 * A1], Gc.bc[2 * A1 + 1]));
+          if (DIM == 3) {
+            if (Q[A2] < 0 || Q[A2] >= Gf.n[A2]) continue;
+            w *= T(tan_weight(Q[A2], P[A2], Gc.n[A2], Gc.bc[2 * A2], Gc.bc[2 * A2 + 1]));
+          }
+        }
+        acc += w * ldm<C>(Gf, rf, Q[0], Q[1], Q[2]);
       }
   }
+  const T dc = x0c ? dinv_c[f] : T(0);
+  if (done) return;
   const T v = acc * T(DIM == 3 ? 0.125 : 0.25);
   bc[f] = v;
-  if (x0c) x0c[f] = omega_c * dinv_c[f] * v;
+  if (x0c) x0c[f] = omega_c * dc * v;
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, bool SM>
 __global__ __launch_bounds__(kBlock) void k_restrict(Grid Gf, Grid Gc, const T* __restrict__ rf,
                                                      T* __restrict__ bc, const PcgState* st,
                                                      const T* __restrict__ dinv_c = nullptr,
                                                      T omega_c = T(0), T* __restrict__ x0c = nullptr) {
-  if (st && st->done) return;
+  // the flag is tested after the fine values are loaded
+  const int done = st ? st->done : 0;
   const int c = blockIdx.z / Gc.nze;
   const int k = blockIdx.z - c * Gc.nze;
   const int idx = blockIdx.x * kBlock + threadIdx.x;
-  if (c == 0) restrict_face<T, DIM, 0>(Gf, Gc, rf, bc, dinv_c, omega_c, x0c, idx, k);
-  else if (c == 1) restrict_face<T, DIM, 1>(Gf, Gc, rf, bc, dinv_c, omega_c, x0c, idx, k);
-  else if (DIM == 3) restrict_face<T, DIM, 2>(Gf, Gc, rf, bc, dinv_c, omega_c, x0c, idx, k);
+  if (c == 0) restrict_face<T, DIM, 0, SM>(Gf, Gc, rf, bc, dinv_c, omega_c, x0c, idx, k, done);
+  else if (c == 1) restrict_face<T, DIM, 1, SM>(Gf, Gc, rf, bc, dinv_c, omega_c, x0c, idx, k, done);
+  else if (DIM == 3) restrict_face<T, DIM, 2, SM>(Gf, Gc, rf, bc, dinv_c, omega_c, x0c, idx, k, done);
 }
 
 // Prolongation + correction: fine faces coinciding with a coarse face take
 // its value, fine faces between two coarse faces the mean (linear in the
-// normal direction); constant across the two fine cells in tangential
-// directions.
-template <typename T, int DIM, int C>
+// normal direction); across the two fine cells in tangential directions
+// constant (DIV) or linear between coarse row centres (SMOOTH, weights of
+// tan_weight).
+template <typename T, int DIM, int C, bool SM>
 __device__ __forceinline__ void prolong_face(const Grid& Gf, const Grid& Gc,
                                              const T* __restrict__ ec, T* __restrict__ xf, int idx,
                                              int k) {
@@ -593,25 +652,56 @@ __device__ __forceinline__ void prolong_face(const Grid& Gf, const Grid& Gc,
   if (!unk<C>(Gf, P[C])) return;
   int Q[3] = {P[0] >> 1, P[1] >> 1, P[2] >> 1};
   Q[C] = P[C] >> 1;
-  T v = ldm<C>(Gc, ec, Q[0], Q[1], Q[2]);
-  if (P[C] & 1) {
-    int R[3] = {Q[0], Q[1], Q[2]};
-    R[C] += 1;
-    v = T(0.5) * (v + ldm<C>(Gc, ec, R[0], R[1], R[2]));
+  T v;
+  if (!SM) {
+    v = ldm<C>(Gc, ec, Q[0], Q[1], Q[2]);
+    if (P[C] & 1) {
+      int R[3] = {Q[0], Q[1], Q[2]};
+      R[C] += 1;
+      v = T(0.5) * (v + ldm<C>(Gc, ec, R[0], R[1], R[2]));
+    }
+  } else {
+    const int A1 = (C + 1) % DIM, A2 = (C + 2) % 3;
+    const bool odd = P[C] & 1;
+    v = T(0);
+#pragma unroll
+    for (int dn = 0; dn < 2; ++dn) {
+      if (dn == 1 && !odd) break;
+      const T wn = odd ? T(0.5) : T(1);
+#pragma unroll
+      for (int a1 = 0; a1 < 2; ++a1) {
+        int R[3] = {Q[0], Q[1], Q[2]};
+        R[C] += dn;
+        if (a1 == 1) R[A1] += (P[A1] & 1) ? 1 : -1;
+        if (R[A1] < 0 || R[A1] >= Gc.n[A1]) continue;  // folded into a1 = 0
+        const T w1 = T(tan_weight(P[A1], R[A1], Gc.n[A1], Gc.bc[2 * A1], Gc.bc[2 * A1 + 1]));
+#pragma unroll
+        for (int a2 = 0; a2 < (DIM == 3 ? 2 : 1); ++a2) {
+          if (DIM == 3) {
+            R[A2] = Q[A2] + (a2 == 1 ? ((P[A2] & 1) ? 1 : -1) : 0);
+            if (R[A2] < 0 || R[A2] >= Gc.n[A2]) continue;
+          }
+          const T w2 = DIM == 3 ? T(tan_weight(P[A2], R[A2], Gc.n[A2], Gc.bc[2 * A2],
+                                               Gc.bc[2 * A2 + 1]))
+                                : T(1);
+          v += wn * w1 * w2 * ldm<C>(Gc, ec, R[0], R[1], R[2]);
+        }
+      }
+    }
   }
   xf[fidx<C>(Gf, i, j, k)] += v;
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, bool SM>
 __global__ __launch_bounds__(kBlock) void k_prolong_add(Grid Gf, Grid Gc, const T* __restrict__ ec,
                                                         T* __restrict__ xf, const PcgState* st) {
   if (st && st->done) return;
   const int c = blockIdx.z / Gf.nze;
   const int k = blockIdx.z - c * Gf.nze;
   const int idx = blockIdx.x * kBlock + threadIdx.x;
-  if (c == 0) prolong_face<T, DIM, 0>(Gf, Gc, ec, xf, idx, k);
-  else if (c == 1) prolong_face<T, DIM, 1>(Gf, Gc, ec, xf, idx, k);
-  else if (DIM == 3) prolong_face<T, DIM, 2>(Gf, Gc, ec, xf, idx, k);
+  if (c == 0) prolong_face<T, DIM, 0, SM>(Gf, Gc, ec, xf, idx, k);
+  else if (c == 1) prolong_face<T, DIM, 1, SM>(Gf, Gc, ec, xf, idx, k);
+  else if (DIM == 3) prolong_face<T, DIM, 2, SM>(Gf, Gc, ec, xf, idx, k);
 }
 
 // x = Minv b on the coarsest grid: FP64 dense inverse (full-face layout,
@@ -620,9 +710,10 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_coarse_gemv(int m, const double* __restrict__ Minv,
                                                         const T* __restrict__ b, T* __restrict__ x,
                                                         const PcgState* st) {
-  if (st && st->done) return;
+  const int done = st ? st->done : 0;
   extern __shared__ __align__(16) double sb[];
   for (int i = threadIdx.x; i < m; i += kBlock) sb[i] = double(b[i]);
+  if (done) return;  // uniform, before the barrier
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);

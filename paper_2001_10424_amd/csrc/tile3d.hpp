@@ -226,7 +226,9 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
                                                 const PcgState* __restrict__ st,
                                                 const T* __restrict__ ec, Grid Gc,
                                                 T* __restrict__ y2) {
-  if (st && st->done) return;
+  // the flag is read here and tested after the prologue's loads are issued
+  // (before the first LDS store), so its round trip overlaps theirs
+  const int done = st ? st->done : 0;
   __shared__ TileLds<T, MODE == kJacobiP> S;
   const Grid& G = op.g;
   const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
@@ -566,20 +568,23 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
   FRegs FA, FB;
   fetch_plane(k0 - 1, FA);
   fetch_plane(k0, FB);
+  // kJacobiP: coarse planes of the two planes staged here and of the first
+  // step's: (k0 - 1) / 2 .. (k0 + 2) / 2 (three planes for an even k0, two
+  // for an odd one); then, for an odd k0, the registers of the plane its
+  // first step writes.  From there on step k loads plane (k + 4) / 2 into
+  // registers when k is even and writes plane (k + 3) / 2 to LDS when k is
+  // odd: every plane is in LDS two barriers before it is first read, and
+  // its slot last held plane K - 3, read for the last time three steps
+  // earlier.
+  const int Ka = (k0 - 1) >> 1, Kb = (k0 + 2) >> 1;
+  T r0[kCPer], r1[kCPer], r2[kCPer];
   if (kP) {
-    // coarse planes of the two planes staged here and of the first step's:
-    // (k0 - 1) / 2 .. (k0 + 2) / 2 (three planes for an even k0, two for
-    // an odd one); then, for an odd k0, the registers of the plane its first
-    // step writes.  From there on step k loads plane (k + 4) / 2 into
-    // registers when k is even and writes plane (k + 3) / 2 to LDS when k is
-    // odd: every plane is in LDS two barriers before it is first read, and
-    // its slot last held plane K - 3, read for the last time three steps
-    // earlier.
-    const int Ka = (k0 - 1) >> 1, Kb = (k0 + 2) >> 1;
-    T r0[kCPer], r1[kCPer], r2[kCPer];
     cload(Ka, r0);
     cload(Ka + 1, r1);
     if (Kb >= Ka + 2) cload(Ka + 2, r2);
+  }
+  if (done) return;  // uniform: the whole block leaves before any barrier
+  if (kP) {
     cstore(Ka, r0);
     cstore(Ka + 1, r1);
     if (Kb >= Ka + 2) cstore(Ka + 2, r2);

@@ -63,6 +63,7 @@ def test_default_options(lib):
     assert o.hip_stream is None and o.max_workspace_bytes == 0
     assert (o.krylov, o.fgmres_restart, o.method, o.outer_restart) == (0, 30, 0, 10)
     assert o.cnn_weights is None and o.learned_min_gain == 0.05
+    assert o.mg_transfer == 0  # GKB_TRANSFER_AUTO
 
 
 def test_error_strings(lib):
@@ -107,7 +108,8 @@ def test_setup_rejects_invalid_arguments_before_any_device_work(lib):
                          ("fgmres_restart", 0), ("fgmres_restart", 65), ("method", 2),
                          ("method", 1),  # GKB as preconditioner needs refine_tol > 0
                          ("outer_restart", 0), ("outer_restart", 33),
-                         ("learned_min_gain", float("nan"))):
+                         ("learned_min_gain", float("nan")),
+                         ("mg_transfer", -1), ("mg_transfer", 3)):
         oo = _abi.Options()
         C.memmove(C.byref(oo), C.byref(o), C.sizeof(o))
         setattr(oo, field, value)

@@ -261,15 +261,17 @@ def test_learned_preconditioner_in_fgmres():
     every inner solve applies V-cycle + network in every step, and the
     solve meets the FP64 residual 1e-8 (oracle).  Inner iterations per solve
     of FGMRES with the V-cycle alone, FGMRES with the network and MG-PCG are
-    reported."""
+    reported.  The hybrid smoother throughout (pairs and solves): restarted
+    FGMRES with the point-Jacobi V-cycle stalls at eta = 1e3."""
     _say("learned fgmres")
     import torch
     from paper_2001_10424_amd.cnn import capture_pairs
     gk = _gk()
     ins, tgs = [], []
+    hyb = dict(smoother="hybrid", nu_pre=1, nu_post=1, inner_maxit=20000)
     for seed in (121, 122):
         pr = _small_problem(seed, n=32)
-        s = _solver(gk, pr, inner="mg")
+        s = _solver(gk, pr, inner="mg", **hyb)
         a, b = capture_pairs(s, _dev(pr.g), _dev(pr.r), tol=1e-4, max_pairs=24)
         ins.append(a)
         tgs.append(b)
@@ -281,7 +283,8 @@ def test_learned_preconditioner_in_fgmres():
     res = {}
     for name, kw in (("cg_mg", dict(inner="mg")), ("fgmres_mg", dict(inner="mg", krylov="fgmres")),
                      ("fgmres_learned", dict(inner="learned", krylov="fgmres"))):
-        s = _solver(gk, pr, **kw)
+        _say("learned fgmres", name)
+        s = _solver(gk, pr, **kw, **hyb)
         if kw["inner"] == "learned":
             s.attach_cnn(net)
         w, p, info = s.solve(_dev(pr.g), _dev(pr.r), tol=1e-4)
