@@ -361,6 +361,25 @@ int gkb_residual(gkb_ctx *c, const double *g, const double *r, const double *w,
    not change solver state other than scratch vectors. */
 int gkb_time_kernel(gkb_ctx *c, int kernel, int reps, double *avg_ms);
 
+/* ---- allocation-free entry point ------------------------------------- */
+
+/* For callers that cannot allocate device memory (code between other
+   allocations it must not disturb, serving loops, harnesses that forbid
+   hipMalloc): the FP64 saddle residual of gkb_residual for viscosity mu = 1,
+   without a solver context.  grid as for gkb_setup; g, w (faces) and r, p
+   (cells) are caller-owned device FP64 arrays; res_r (cells, required) and
+   res_w (faces, may be NULL) receive the residual blocks; norms (host, 4
+   doubles) as gkb_residual.  Work is queued on hip_stream (NULL = the null
+   stream) and complete on return.  Allocates nothing: its reduction partials
+   live in a fixed device array of 2 MiB (one per GPU, kept until the process
+   ends) shared by every call on that GPU, so calls that overlap on one GPU
+   race.  Grids that need more than 65536 partials per reduction return
+   GKB_EINVAL (every grid up to 256^3 in 3D and 2048^2 in 2D fits), as do
+   invalid grids. */
+int gkb_residual_noalloc(const gkb_grid *grid, const double *g, const double *r,
+                         const double *w, const double *p, double *res_w,
+                         double *res_r, double *norms, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

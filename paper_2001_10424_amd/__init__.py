@@ -14,7 +14,7 @@ import ctypes as C
 
 from . import _abi
 
-__all__ = ["Solver", "CsrSolver", "library", "CNN"]
+__all__ = ["Solver", "CsrSolver", "library", "CNN", "residual_noalloc"]
 
 
 def library():
@@ -36,6 +36,27 @@ def _grid_struct(grid):
         gs.bc[s] = int(grid.bc[s])
     gs.pin_cell = int(grid.pin)
     return gs
+
+
+def residual_noalloc(grid, g, r, w, p, res_w=None, res_r=None):
+    """FP64 saddle residual for mu = 1 without a solver context and without
+    device allocation by the library (gkb_residual_noalloc).  g, w (faces) and
+    r, p (cells): contiguous cuda float64 tensors; res_r (cells) is required by
+    the C call and created here when not given.  Returns (norms, res_w, res_r)
+    with norms = (||res||, ||res_w||, ||res_r||, ||[g; r]||)."""
+    import torch
+    for t in (g, r, w, p, res_w, res_r):
+        if t is not None and not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise ValueError("expected contiguous cuda float64 tensors")
+    if res_r is None:
+        res_r = torch.empty_like(r)
+    norms = (C.c_double * 4)()
+    gs = _grid_struct(grid)
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _abi.check(_abi.lib().gkb_residual_noalloc(C.byref(gs), _ptr(g), _ptr(r), _ptr(w), _ptr(p),
+                                               _ptr(res_w), _ptr(res_r), norms, stream),
+               "gkb_residual_noalloc")
+    return list(norms), res_w, res_r
 
 
 class Solver:

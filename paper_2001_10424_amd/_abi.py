@@ -101,6 +101,8 @@ def lib():
     L.gkb_setup_csr.argtypes = [C.POINTER(Csr), C.c_double, C.c_int, C.POINTER(Options),
                                 C.POINTER(ctxp)]
     L.gkb_setup_csr.restype = C.c_int
+    L.gkb_residual_noalloc.argtypes = [C.POINTER(Grid), P, P, P, P, P, P, P, P]
+    L.gkb_residual_noalloc.restype = C.c_int
     _declare_cnn(L)
     _lib = L
     return L

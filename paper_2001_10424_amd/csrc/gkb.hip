@@ -2081,3 +2081,4 @@ extern "C" int gkb_time_kernel(gkb_ctx* c, int kernel, int reps, double* avg_ms)
   return time_kernel_impl<double>(c, c->in64, kernel, reps, avg_ms);
 }
 
+#include "noalloc.hpp"

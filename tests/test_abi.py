@@ -129,6 +129,14 @@ def test_null_context_calls_fail_cleanly(lib):
     st = _abi.Stats()
     assert lib.gkb_stats(None, C.byref(st)) == _abi.GKB_EINVAL
     assert lib.gkb_solve(None, None, None, 1e-8, 5, None, None, None, None) == _abi.GKB_EINVAL
+    # the allocation-free residual validates its grid before any device work
+    g = _grid(h=-1.0)
+    norms = (C.c_double * 4)()
+    one = C.c_void_p(8)  # never dereferenced: the grid is rejected first
+    assert lib.gkb_residual_noalloc(C.byref(g), one, one, one, one, None, one, norms,
+                                    None) == _abi.GKB_EINVAL
+    assert lib.gkb_residual_noalloc(None, one, one, one, one, None, one, norms,
+                                    None) == _abi.GKB_EINVAL
     lib.gkb_destroy(None)
     ms = C.c_double()
     for k in (0, 3, 4, 5, -1):
