@@ -509,7 +509,7 @@ template <>
 const Op<float>& op_of<float>(gkb_ctx* c) { return c->op32; }
 
 template <typename T>
-void pcg_iterations(gkb_ctx* c, Inner<T>& in, int count) {
+int pcg_iterations(gkb_ctx* c, Inner<T>& in, int count) {
   const Level<T>& L0 = in.lv[0];
   const int n = L0.g.m_full, vb = vec_blocks(n);
   hipStream_t s = c->cs;
@@ -545,6 +545,7 @@ void pcg_iterations(gkb_ctx* c, Inner<T>& in, int count) {
     }
     if (!fused) k_pcg_p<T><<<vb, kBlock, 0, s>>>(n, in.st, in.z, in.p);
   }
+  return GKB_OK;
 }
 
 template <typename T>
@@ -558,10 +559,16 @@ int ensure_graph(gkb_ctx* c, Inner<T>& in, int count) {
   }
   hipGraph_t gr;
   HIPCK(hipStreamBeginCapture(c->cs, hipStreamCaptureModeThreadLocal));
-  pcg_iterations<T>(c, in, count);
-  HIPCK(hipStreamEndCapture(c->cs, &gr));
-  HIPCK(hipGraphInstantiate(&in.graph, gr, nullptr, nullptr, 0));
+  const int prc = pcg_iterations<T>(c, in, count);
+  const hipError_t ce = hipStreamEndCapture(c->cs, &gr);
+  if (prc < 0) {
+    if (ce == hipSuccess) (void)hipGraphDestroy(gr);
+    return prc;
+  }
+  HIPCK(ce);
+  const hipError_t ie = hipGraphInstantiate(&in.graph, gr, nullptr, nullptr, 0);
   (void)hipGraphDestroy(gr);
+  HIPCK(ie);
   in.graph_len = count;
   in.graph_mode = key;
   return GKB_OK;
@@ -693,7 +700,7 @@ int inner_solve(gkb_ctx* c, const double* f, double* x_out, double tol, int* ite
     if (c->opt.use_graphs) {
       HIPCK(hipGraphLaunch(in.graph, s));
     } else {
-      pcg_iterations<T>(c, in, chunk);
+      CK(pcg_iterations<T>(c, in, chunk));
     }
     HIPCK(hipMemcpyAsync(c->hbuf, in.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
     HIPCK(hipStreamSynchronize(s));

@@ -541,7 +541,7 @@ int capture_solve(gkb_ctx* c, const double* f, double* x_out, double tol, int* i
         k_cast<T, T><<<vb, kBlock, 0, s>>>(n, in.x, static_cast<T*>(L->snaps[2 * k + 1]));
         taken[k] = 1;
       }
-    pcg_iterations<T>(c, in, 1);
+    CK(pcg_iterations<T>(c, in, 1));
     HIPCK(hipMemcpyAsync(c->hbuf, in.st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
     HIPCK(hipStreamSynchronize(s));
     std::memcpy(&hs, c->hbuf, sizeof(PcgState));

@@ -20,8 +20,7 @@
 // step needs no separate pass over memory: kJacobiZ stages x1 = omega b / D
 // (the first sweep from a zero guess; the kernel then applies the second),
 // and kJacobiP stages x + P e, the prolongation of the coarse-grid
-// correction e, read from a ring of coarse planes in LDS that the block
-// loads once per two fine planes.
+// correction e.
 #pragma once
 #include "kernels.hpp"
 
@@ -38,21 +37,12 @@ constexpr int kTY = kTYT * kRPT; // tile height (cells)
 constexpr int kLX = kTX + 2;
 constexpr int kLY = kTY + 2;
 
-// coarse-grid tile of the prolongation in kJacobiP: coarse faces
-// I in [i0/2 - 1, i0/2 + kTX/2] and J in [j0/2 - 1, j0/2 + kTY/2] cover every
-// staged fine face and its neighbours along the normal
-constexpr int kCX = kTX / 2 + 2;
-constexpr int kCY = kTY / 2 + 2;
-constexpr int kCPlane = 3 * kCY * kCX;  // u, v, w values of one coarse plane
-
-template <typename T, bool PROLONG>
+template <typename T>
 struct TileLds {
   T u[2][kLY][kLX];
   T v[2][kLY][kLX];
   T w[2][kLY][kLX];
   T cd[kTY + 1][kTX + 1];
-  // kJacobiP: three coarse planes (slot = K mod 3), components u, v, w
-  T cc[PROLONG ? 3 : 1][3][kCY][PROLONG ? kCX : 1];
 };
 
 // one axis of the viscous stencil; lo_in / hi_in: neighbour inside the array,
@@ -226,10 +216,8 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
                                                 const PcgState* __restrict__ st,
                                                 const T* __restrict__ ec, Grid Gc,
                                                 T* __restrict__ y2) {
-  // the flag is read here and tested after the prologue's loads are issued
-  // (before the first LDS store), so its round trip overlaps theirs
-  const int done = st ? st->done : 0;
-  __shared__ TileLds<T, MODE == kJacobiP> S;
+  if (st && st->done) return;
+  __shared__ TileLds<T> S;
   const Grid& G = op.g;
   const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
   // XCD-aware block order: consecutive logical tiles on the same XCD
@@ -279,29 +267,23 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
   // correction e on the grid Gc (a fine face on a coarse face takes its
   // value, a face between two coarse faces their mean; constant across the
   // two fine cells in the tangential directions; non-unknown coarse faces
-  // count as 0).  The coarse values come from a ring of three coarse planes
-  // in LDS (slot K mod 3, zeros outside the coarse grid and at non-unknown
-  // faces), each loaded once per block by all threads: staging fine plane p
-  // reads coarse planes p/2 and (p+1)/2.  Per staged element: the local
-  // coarse column li = I - i0/2 + 1 and row lj = J - j0/2 + 1 of (i/2, j/2)
-  // and the parities of i and j.
+  // count as 0).  Per staged element: in-plane index of the coarse u and v
+  // faces at (i/2, j/2) (w shares v's: both arrays are nx/2 wide) and six
+  // bits: odd i, odd j, coarse u faces I and I+1 unknown, coarse v faces J
+  // and J+1 unknown.  The coarse values (faces I / I+1, J / J+1, coarse
+  // planes K / K+1) are prefetched with the plane.
   constexpr bool kP = MODE == kJacobiP;
   // kApplyDotP: the staged values are p' = z + beta p (x = z, b = p); p is
   // loaded with z into the second register set, p' is written to y2 at the
   // block's own faces
   constexpr bool kAP = MODE == kApplyDotP;
-  constexpr int kPC = kAP ? 3 : 1;
+  constexpr int kPC = kP ? 6 : (kAP ? 3 : 1);
   const T pbeta = (kAP && st) ? T(st->beta) : T(0);
   const __amdgpu_buffer_rsrc_t rpo = kAP ? buf_rsrc(b, bytes) : rx;
   const __amdgpu_buffer_rsrc_t ry2 = kAP ? buf_rsrc(y2, bytes) : ry;
-  unsigned pli[kPer];
+  unsigned pcu[kPer], pcv[kPer], pbits = 0;
   const __amdgpu_buffer_rsrc_t rc = kP ? buf_rsrc(ec, unsigned(Gc.m_full) * E) : rx;
-  // coarse-plane loads of this thread: elements e = threadIdx.x + 256 q2 of
-  // the kCPlane values (component, row, column); in-plane byte offset,
-  // component and in-plane validity (in the array and an unknown face)
-  constexpr int kCPer = (kCPlane + 255) / 256;
-  unsigned cofs[kCPer], cpl[kCPer];  // in-plane byte offset, plane stride (bytes)
-  unsigned cinfo = 0;  // per q2: bits 0-1 component, bit 2 valid, bit 3 exists
+  const unsigned dwc = kP ? unsigned(Gc.off[2] - Gc.off[1]) * E : 0u;
   if (kP) {
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
@@ -309,64 +291,18 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
       const int jj = e / kLX, ii = e - jj * kLX;
       const int i = i0 - 1 + ii, j = j0 - 1 + jj;
       const bool in = (hmask >> (3 * q + 2)) & 1u;
-      const int li = in ? (i >> 1) - (i0 >> 1) + 1 : 0, lj = in ? (j >> 1) - (j0 >> 1) + 1 : 0;
-      pli[q] = unsigned(li) | (unsigned(lj) << 8) | ((in && (i & 1)) ? 1u << 16 : 0u) |
-               ((in && (j & 1)) ? 1u << 17 : 0u);
-    }
-    const int nxc = Gc.n[0], nyc = Gc.n[1];
-#pragma unroll
-    for (int q = 0; q < kCPer; ++q) {
-      const int e = threadIdx.x + q * 256;
-      const int comp = e / (kCY * kCX), rem = e - comp * (kCY * kCX);
-      const int lj = rem / kCX, li = rem - lj * kCX;
-      const int I = (i0 >> 1) - 1 + li, J = (j0 >> 1) - 1 + lj;
-      const bool exists = e < kCPlane;
-      // component data by arithmetic selection (an indexed pick would put
-      // the grid description in scratch memory)
-      const int s0 = comp == 0, s1 = comp == 1, s2 = comp >= 2;
-      const int off = s0 * Gc.off[0] + s1 * Gc.off[1] + s2 * Gc.off[2];
-      const int ex0 = s0 * Gc.ext[0][0] + s1 * Gc.ext[1][0] + s2 * Gc.ext[2][0];
-      const int ex1 = s0 * Gc.ext[0][1] + s1 * Gc.ext[1][1] + s2 * Gc.ext[2][1];
-      const bool uok = I >= 0 && I <= nxc && J >= 0 && J < nyc &&
-                       !((I == 0 && Gc.bc[0] == kDir) || (I == nxc && Gc.bc[1] == kDir));
-      const bool vok = I >= 0 && I < nxc && J >= 0 && J <= nyc &&
-                       !((J == 0 && Gc.bc[2] == kDir) || (J == nyc && Gc.bc[3] == kDir));
-      const bool wok = I >= 0 && I < nxc && J >= 0 && J < nyc;
-      const bool ok = exists && (s0 ? uok : (s1 ? vok : wok));
-      cofs[q] = ok ? unsigned(off + J * ex0 + I) * E : 0u;
-      cpl[q] = unsigned(ex0 * ex1) * E;
-      cinfo |= (unsigned(comp < 3 ? comp : 0) | (ok ? 4u : 0u) | (exists ? 8u : 0u)) << (4 * q);
+      const int I = in ? i >> 1 : 0, J = in ? j >> 1 : 0;
+      pcu[q] = unsigned(Gc.off[0] + J * Gc.ext[0][0] + I) * E;
+      pcv[q] = unsigned(Gc.off[1] + J * Gc.ext[1][0] + I) * E;
+      const bool uI = !((I == 0 && Gc.bc[0] == kDir) || (I == Gc.n[0] && Gc.bc[1] == kDir));
+      const bool uI1 = !(I + 1 == Gc.n[0] && Gc.bc[1] == kDir);
+      const bool vJ = !((J == 0 && Gc.bc[2] == kDir) || (J == Gc.n[1] && Gc.bc[3] == kDir));
+      const bool vJ1 = !(J + 1 == Gc.n[1] && Gc.bc[3] == kDir);
+      const unsigned bits = (i & 1 ? 1u : 0u) | (j & 1 ? 2u : 0u) | (uI ? 4u : 0u) |
+                            (uI1 ? 8u : 0u) | (vJ ? 16u : 0u) | (vJ1 ? 32u : 0u);
+      pbits |= bits << (6 * q);
     }
   }
-  // load coarse plane K into registers: zero where the face is not an
-  // unknown or K is outside the component's planes (u, v: 0 .. nz_c - 1;
-  // w: 0 .. nz_c, the DIRICHLET ends excluded)
-  T creg[kCPer];
-  auto cload = [&](int K, T (&r)[kCPer]) {
-    const int nzc = Gc.n[2];
-    const bool okuv = K >= 0 && K < nzc;
-    const bool okw = K >= 0 && K <= nzc && !((K == 0 && Gc.bc[4] == kDir) ||
-                                             (K == nzc && Gc.bc[5] == kDir));
-#pragma unroll
-    for (int q = 0; q < kCPer; ++q) {
-      const unsigned inf = cinfo >> (4 * q);
-      const bool ok = (inf & 4u) && ((inf & 3u) == 2u ? okw : okuv);
-      const T v = buf_load<T>(rc, cofs[q], unsigned(ok ? K : 0) * cpl[q]);
-      r[q] = ok ? v : T(0);
-    }
-  };
-  auto cstore = [&](int K, const T (&r)[kCPer]) {
-    const int sl = (K + 3) % 3;  // K >= -1
-#pragma unroll
-    for (int q = 0; q < kCPer; ++q) {
-      const int e = threadIdx.x + q * 256;
-      if ((cinfo >> (4 * q)) & 8u) {
-        const int comp = e / (kCY * kCX), rem = e - comp * (kCY * kCX);
-        const int lj = rem / kCX, li = rem - lj * kCX;
-        S.cc[sl][comp][lj][kP ? li : 0] = r[q];
-      }
-    }
-  };
   struct FRegs {
     T v[3][kPer];
     T c[kPC][kPer];  // kJacobiP: coarse u(I), u(I+1), v(J), v(J+1), w(K), w(K+1)
@@ -385,6 +321,27 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
         F.c[0][q] = buf_load<T>(rpo, hu[q], unsigned(kk * pu) * E);
         F.c[1][q] = buf_load<T>(rpo, hv[q], unsigned(kk * pv) * E);
         F.c[2][q] = buf_load<T>(rpo, hv[q], unsigned(kk * pw) * E + dw);
+      }
+    }
+    if (kP) {
+      const int K = kk >> 1, K1 = min(K + 1, Gc.ext[2][2] - 1);
+      const unsigned su = unsigned(K * Gc.ext[0][0] * Gc.ext[0][1]) * E;
+      const unsigned sv = unsigned(K * Gc.ext[1][0] * Gc.ext[1][1]) * E;
+      const unsigned sw = unsigned(K * Gc.ext[2][0] * Gc.ext[2][1]) * E + dwc;
+      const unsigned sw1 = unsigned(K1 * Gc.ext[2][0] * Gc.ext[2][1]) * E + dwc;
+      const unsigned rowv = unsigned(Gc.ext[1][0]) * E;
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        F.c[0][q] = buf_load<T>(rc, pcu[q], su);
+        F.c[1][q] = buf_load<T>(rc, pcu[q] + E, su);
+        F.c[2][q] = buf_load<T>(rc, pcv[q], sv);
+        F.c[3][q] = buf_load<T>(rc, pcv[q] + rowv, sv);
+        F.c[4][q] = buf_load<T>(rc, pcv[q], sw);
+      }
+      // the coarse plane above is needed by the w faces of odd planes only
+      if (kk & 1) {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) F.c[5][q] = buf_load<T>(rc, pcv[q], sw1);
       }
     }
   };
@@ -429,24 +386,19 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
 #pragma unroll
       for (int c = 0; c < 3; ++c) val[c][q] = kAP ? F.v[c][q] + pbeta * F.c[c][q] : F.v[c][q];
     if (kP && kin) {
-      // coarse plane K = k / 2 (slot K mod 3); a w face on an odd plane lies
-      // between K and K + 1
+      // coarse plane K = k / 2; a w face on an odd plane lies between K and K+1
       const int K = k >> 1;
-      const int s0 = (K + 3) % 3, s1 = (K + 4) % 3;
+      const bool wK = !((K == 0 && Gc.bc[4] == kDir) || (K == Gc.n[2] && Gc.bc[5] == kDir));
+      const bool wK1 = !(K + 1 == Gc.n[2] && Gc.bc[5] == kDir);
       const bool oddk = k & 1;
 #pragma unroll
       for (int q = 0; q < kPer; ++q) {
-        const unsigned pq = pli[q];
-        const int li = int(pq & 0xffu), lj = int((pq >> 8) & 0xffu);
-        const bool oi = (pq >> 16) & 1u, oj = (pq >> 17) & 1u;
-        const T u0 = S.cc[s0][0][lj][kP ? li : 0];
-        const T v0 = S.cc[s0][1][lj][kP ? li : 0];
-        const T w0 = S.cc[s0][2][lj][kP ? li : 0];
-        const T u1 = oi ? S.cc[s0][0][lj][kP ? li + 1 : 0] : T(0);
-        const T v1 = oj ? S.cc[s0][1][lj + 1][kP ? li : 0] : T(0);
-        const T w1 = oddk ? S.cc[s1][2][lj][kP ? li : 0] : T(0);
-        val[0][q] += oi ? T(0.5) * (u0 + u1) : u0;
-        val[1][q] += oj ? T(0.5) * (v0 + v1) : v0;
+        const unsigned bq = pbits >> (6 * q);
+        const T u0 = (bq & 4u) ? F.c[0][q] : T(0), u1 = (bq & 8u) ? F.c[1][q] : T(0);
+        const T v0 = (bq & 16u) ? F.c[2][q] : T(0), v1 = (bq & 32u) ? F.c[3][q] : T(0);
+        const T w0 = wK ? F.c[4][q] : T(0), w1 = wK1 ? F.c[5][q] : T(0);
+        val[0][q] += (bq & 1u) ? T(0.5) * (u0 + u1) : u0;
+        val[1][q] += (bq & 2u) ? T(0.5) * (v0 + v1) : v0;
         val[2][q] += oddk ? T(0.5) * (w0 + w1) : w0;
       }
     }
@@ -568,29 +520,6 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
   FRegs FA, FB;
   fetch_plane(k0 - 1, FA);
   fetch_plane(k0, FB);
-  // kJacobiP: coarse planes of the two planes staged here and of the first
-  // step's: (k0 - 1) / 2 .. (k0 + 2) / 2 (three planes for an even k0, two
-  // for an odd one); then, for an odd k0, the registers of the plane its
-  // first step writes.  From there on step k loads plane (k + 4) / 2 into
-  // registers when k is even and writes plane (k + 3) / 2 to LDS when k is
-  // odd: every plane is in LDS two barriers before it is first read, and
-  // its slot last held plane K - 3, read for the last time three steps
-  // earlier.
-  const int Ka = (k0 - 1) >> 1, Kb = (k0 + 2) >> 1;
-  T r0[kCPer], r1[kCPer], r2[kCPer];
-  if (kP) {
-    cload(Ka, r0);
-    cload(Ka + 1, r1);
-    if (Kb >= Ka + 2) cload(Ka + 2, r2);
-  }
-  if (done) return;  // uniform: the whole block leaves before any barrier
-  if (kP) {
-    cstore(Ka, r0);
-    cstore(Ka + 1, r1);
-    if (Kb >= Ka + 2) cstore(Ka + 2, r2);
-    if (k0 & 1) cload((k0 + 3) >> 1, creg);
-    __syncthreads();
-  }
   store_plane(1, k0 - 1, FA);
   store_plane(0, k0, FB);
   // planes k0+1 (FA) and k0+2 (FB), b of planes k0 (bA) and k0+1 (bB)
@@ -625,10 +554,6 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
     store_plane(s1, k + 1, F);
     __syncthreads();
     fetch_plane(min(k + 3, k1), F);
-    if (kP) {
-      if (k & 1) cstore((k + 3) >> 1, creg);
-      else cload((k + 4) >> 1, creg);
-    }
     // divergence sums of plane k for cells (i0-1 .. i0+63) x (j0-1 .. j0+7)
     for (int e = threadIdx.x; e < (kTX + 1) * (kTY + 1); e += 256) {
       const int cj = e / (kTX + 1), ci = e - cj * (kTX + 1);
@@ -767,10 +692,6 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
     store_plane(s1, k + 1, F);
     __syncthreads();
     fetch_plane(min(k + 3, k1), F);
-    if (kP) {
-      if (k & 1) cstore((k + 3) >> 1, creg);
-      else cload((k + 4) >> 1, creg);
-    }
     const bool pz = k == pk;
     const bool kbulk = k > 0 && k < nz - 1 && k != pk && k - 1 != pk;
     if (!kbulk) coef(k, false);  // uniform branch

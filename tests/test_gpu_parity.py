@@ -147,7 +147,7 @@ MMS_CASES = [
     # these grids the oracle's own pressure moves by 4e-10 - 6e-10 under a
     # relative 1e-15 perturbation of g (measured on the CPU), so those cases
     # compare p at 5e-9 and w at 1e-10 (and the zeta history to 1e-10 of
-    # zeta_1 instead of 1e-13); at eta <= 10 that movement is below 3e-11 and
+    # zeta_1 instead of 1e-12); at eta <= 10 that movement is below 3e-11 and
     # both are compared at 1e-10.
     ("2d_pin_eta0", P.Grid(2, (20, 14, 1), 1 / 20, (D,) * 6, 3), 0.0, False, 9, 1e-10),
     ("2d_pin_eta10_varmu", P.Grid(2, (18, 16, 1), 1 / 18, (D,) * 6, 0), 10.0, True, 8, 1e-10),
@@ -184,8 +184,11 @@ def test_manufactured_rhs_gkb_parity(name, grid, eta, varmu, K, p_tol):
     w, p, info, ref = _gkb_pair(pr, 0.0, K, mu=pr.mu)
     assert info["status"] == 1 and ref["status"] == 1 and info["iterations"] == ref["K"] == K
     assert _rel(w, ref["w"]) <= 1e-10 and _rel(p, ref["p"]) <= p_tol
-    # the smallest zeta values carry the same sensitivity as p
-    z_atol = 1e-13 if p_tol <= 1e-10 else 1e-10
+    # the smallest zeta values carry the same sensitivity as p; with inner
+    # solves stopped at relative 1e-13 each zeta_k is fixed only to about
+    # 10 tau_in |zeta_1| (the oracle's own OpenMP reductions move it by that
+    # much with the host's thread count)
+    z_atol = 1e-12 if p_tol <= 1e-10 else 1e-10
     np.testing.assert_allclose(info["zeta"], ref["zeta"], rtol=1e-9,
                                atol=z_atol * abs(ref["zeta"][0]))
     w, p, info, ref = _gkb_pair(pr, 1e-10, 400, mu=pr.mu)
