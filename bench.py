@@ -351,22 +351,35 @@ def study_learned(gk, torch, problems, dim, train_seeds, eval_seeds, steps=1500)
                 maxit=200, refine_tol=1e-8, max_sweeps=30)
     t0 = time.perf_counter()
     ins, tgs = [], []
-    for sd in train_seeds:
+    # capture solves: inner tolerance 1e-5 in 2D; in 3D the evaluation's 3e-4
+    # and at most 2000 inner iterations, so that a capture solve stays short
+    cap = dict(base, inner_tol=1e-5) if dim == 2 else dict(base, inner_tol=3e-4,
+                                                             inner_maxit=2000)
+    for i, sd in enumerate(train_seeds):
+        if dim == 3:
+            log(f"[study] capturing seed {sd}, {time.perf_counter() - t0:.1f} s")
         pr = problems.stokes_problem(dim, n, seed=sd, eta=1e3, mu_seed=mu_seed)
-        s = gk.Solver(pr.grid, pr.mu, pr.eta, precision="mixed", inner_tol=1e-5, **base)
+        s = gk.Solver(pr.grid, pr.mu, pr.eta, precision="mixed", **cap)
         a, b = capture_pairs(s, torch.tensor(pr.g, device="cuda"),
                              torch.tensor(pr.r, device="cuda"), tol=3e-3, max_pairs=8, delay=2)
         ins.append(a)
         tgs.append(b)
         s.close()
+        if dim == 3 or i % 32 == 31:
+            log(f"[study] captured seed {sd}: {sum(x.shape[0] for x in ins)} pairs, "
+                f"{time.perf_counter() - t0:.1f} s")
     inputs, targets = torch.cat(ins).contiguous(), torch.cat(tgs).contiguous()
     del ins, tgs
     t1 = time.perf_counter()
     net = gk.CNN(dim, channels, seed=0)
     shape = (n, n, 1) if dim == 2 else (n, n, n)
     loss0 = net.evaluate(inputs, targets, shape)
-    net.train(inputs, targets, shape, crop=crop, batch=8 if dim == 2 else 2, steps=steps,
-              lr=1e-3 if dim == 2 else 1e-4, seed=1)
+    # chunks of 100 steps (Adam's moments and step count live in the network,
+    # so the chunks continue one run; each chunk draws its crops from its own seed)
+    for c0 in range(0, steps, 100):
+        net.train(inputs, targets, shape, crop=crop, batch=8 if dim == 2 else 2,
+                  steps=min(100, steps - c0), lr=1e-3 if dim == 2 else 1e-4, seed=1 + c0)
+        log(f"[study] trained {min(c0 + 100, steps)} steps, {time.perf_counter() - t1:.1f} s")
     loss1 = net.evaluate(inputs, targets, shape)
     t2 = time.perf_counter()
     train = dict(pairs=int(inputs.shape[0]), capture_s=round(t1 - t0, 2), train_s=round(t2 - t1, 2),
@@ -384,12 +397,19 @@ def study_learned(gk, torch, problems, dim, train_seeds, eval_seeds, steps=1500)
         g = torch.tensor(pr.g, device="cuda")
         r = torch.tensor(pr.r, device="cuda")
         for name, kw in modes.items():
+            log(f"[study] seed {sd}: {name}")
             opts = dict(base, **kw)
             s = gk.Solver(pr.grid, pr.mu, pr.eta, **opts)
             if opts["inner"] == "learned":
                 s.attach_cnn(net)
-            s.solve(g, r, tol=3e-3, delay=2)
-            dt, w, p, info = timed_solve(torch, s, g, r, 3e-3, 2)
+            try:
+                s.solve(g, r, tol=3e-3, delay=2)
+                log(f"[study] seed {sd}: {name} warm-up solve done")
+                dt, w, p, info = timed_solve(torch, s, g, r, 3e-3, 2)
+            except RuntimeError as e:  # reported, the study goes on
+                s.close()
+                print(json.dumps(dict(mode=name, seed=sd, error=str(e))), flush=True)
+                continue
             norms, _, _ = s.residual(g, r, w, p)
             s.close()
             row = dict(mode=name, seed=sd, seconds=round(dt, 4), residual=norms[0] / norms[3],

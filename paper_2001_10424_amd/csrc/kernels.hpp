@@ -409,6 +409,51 @@ __global__ __launch_bounds__(kFinal) void k_pcg_start(PcgState* st, const double
   }
 }
 
+// Scalar steps of PCG on the device state (one thread): alpha from p.q;
+// the convergence test on r.r (with rz: also beta, Jacobi path); beta from
+// the new r.z.
+__device__ __forceinline__ void pcg_set_alpha(PcgState* st, double pq) {
+  st->pq = pq;
+  const double a = st->rz / pq;
+  if (!(pq > 0.0) || !isfinite(a)) {
+    st->alpha = 0.0;
+    st->nonfinite = 1;
+    st->status = -4;
+    st->done = 1;
+  } else {
+    st->alpha = a;
+  }
+}
+__device__ __forceinline__ void pcg_set_check(PcgState* st, double rr, bool has_rz, double rz) {
+  st->rr = rr;
+  st->it += 1;
+  // r.r sampled every 5 iterations: stagnant when no decrease over 50
+  // (CG minimises the energy norm, so r.r may rise over shorter spans)
+  if (st->it % 5 == 0) {
+    const int slot = (st->it / 5) % 10;
+    if (st->it > 50 && rr >= st->ring[slot]) st->stagnant = 1;
+    st->ring[slot] = rr;
+  }
+  if (!isfinite(rr)) {
+    st->nonfinite = 1;
+    st->status = -4;
+    st->done = 1;
+  } else if (rr <= st->tol2 * st->rr0) {
+    st->done = 1;
+    st->status = 0;
+  } else if (st->it >= st->maxit) {
+    st->done = 1;
+    st->status = -5;
+  } else if (has_rz) {
+    st->beta = rz / st->rz;
+    st->rz = rz;
+  }
+}
+__device__ __forceinline__ void pcg_set_beta(PcgState* st, double rz) {
+  st->beta = rz / st->rz;
+  st->rz = rz;
+}
+
 // The one-block scalar kernels below read the done flag together with the
 // partials (the flag is tested once both loads are in flight).
 __global__ __launch_bounds__(kFinal) void k_pcg_alpha(PcgState* st, const double* part_pq, int n) {
@@ -417,18 +462,7 @@ __global__ __launch_bounds__(kFinal) void k_pcg_alpha(PcgState* st, const double
   if (done) return;
   __shared__ double sh[kFinal / 64];
   const double pq = block_sum<kFinal>(v, sh);
-  if (threadIdx.x == 0) {
-    st->pq = pq;
-    const double a = st->rz / pq;
-    if (!(pq > 0.0) || !isfinite(a)) {
-      st->alpha = 0.0;
-      st->nonfinite = 1;
-      st->status = -4;
-      st->done = 1;
-    } else {
-      st->alpha = a;
-    }
-  }
+  if (threadIdx.x == 0) pcg_set_alpha(st, pq);
 }
 
 // x += alpha p, r -= alpha q; partial r.r; Jacobi (dinv != null): z = dinv r
@@ -483,31 +517,7 @@ __global__ __launch_bounds__(kFinal) void k_pcg_check(PcgState* st, const double
     __syncthreads();
     rz = block_sum<kFinal>(vrz, sh);
   }
-  if (threadIdx.x == 0) {
-    st->rr = rr;
-    st->it += 1;
-    // r.r sampled every 5 iterations: stagnant when no decrease over 50
-    // (CG minimises the energy norm, so r.r may rise over shorter spans)
-    if (st->it % 5 == 0) {
-      const int slot = (st->it / 5) % 10;
-      if (st->it > 50 && rr >= st->ring[slot]) st->stagnant = 1;
-      st->ring[slot] = rr;
-    }
-    if (!isfinite(rr)) {
-      st->nonfinite = 1;
-      st->status = -4;
-      st->done = 1;
-    } else if (rr <= st->tol2 * st->rr0) {
-      st->done = 1;
-      st->status = 0;
-    } else if (st->it >= st->maxit) {
-      st->done = 1;
-      st->status = -5;
-    } else if (part_rz) {
-      st->beta = rz / st->rz;
-      st->rz = rz;
-    }
-  }
+  if (threadIdx.x == 0) pcg_set_check(st, rr, part_rz != nullptr, rz);
 }
 
 // preconditioned path: rz_new from the partials of the last V-cycle kernel
@@ -517,10 +527,7 @@ __global__ __launch_bounds__(kFinal) void k_pcg_beta(PcgState* st, const double*
   if (done) return;
   __shared__ double sh[kFinal / 64];
   const double rz = block_sum<kFinal>(v, sh);
-  if (threadIdx.x == 0) {
-    st->beta = rz / st->rz;
-    st->rz = rz;
-  }
+  if (threadIdx.x == 0) pcg_set_beta(st, rz);
 }
 
 // p = z + beta p

@@ -61,6 +61,10 @@ def test_forward_matches_reference(dim, channels, shape):
     y = net.forward(torch.tensor(x, device="cuda")).cpu().numpy()
     ref = _ref_forward_bf16(x, params, dim, channels)
     err = np.abs(y - ref).max() / np.abs(ref).max()
+    err2 = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    flips = np.mean(np.abs(y - ref) > 1e-5 * np.abs(ref).max())
+    print(f"[case] forward {dim}D {channels}: max {err:.2e} l2 {err2:.2e} "
+          f"fraction above 1e-5: {flips:.2e}", flush=True)
     assert err <= 1e-2, err
     # one layer: only the FP32 accumulation order differs
     one = gk.CNN(dim, (channels[0], channels[1]), seed=5)
@@ -89,6 +93,7 @@ def test_gradients_match_reference(dim, channels, shape):
     # make the multi-layer comparison loose; the one-layer check below is tight
     eg = np.linalg.norm(g - gr) / np.linalg.norm(gr)
     ex = np.linalg.norm(dx.cpu().numpy() - dxr) / np.linalg.norm(dxr)
+    print(f"[case] backward {dim}D {channels}: grad {eg:.2e} dx {ex:.2e}", flush=True)
     assert eg <= 2e-2 and ex <= 6e-2, (eg, ex)
     # per layer: weight and bias blocks each agree
     o = 0
