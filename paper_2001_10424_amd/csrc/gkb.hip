@@ -374,6 +374,16 @@ void edge_step(gkb_ctx* c, Level<T>& L, const T* b, T* x, const PcgState* st) {
   else k_edge_smooth<T, 3><<<cg, kBlock, 0, s>>>(L.g, L.rb, L.edinv, T(L.omega_e), x, st);
 }
 
+// first smoothing sweep from a zero guess, x = omega D^-1 b, from 1 / D
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_jacobi_first(int n, T omega, const T* __restrict__ dinv,
+                                                         const T* __restrict__ b,
+                                                         T* __restrict__ x, const PcgState* st) {
+  if (st && st->done) return;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+    x[i] = omega * dinv[i] * b[i];
+}
+
 // first_done: the first pre-smoothing sweep from a zero guess is already in
 // its output buffer (written by the restriction into this level)
 template <typename T>
@@ -409,7 +419,17 @@ void vcycle(gkb_ctx* c, Inner<T>& in, int l, const T* b, T* x, double* dot_parti
       cur = dst(k);
     } else {
       T* o = dst(k);
-      if (!first_done) face_op<T, kJacobi0>(c, L.op, L.fl, nullptr, b, o, om, nullptr, st);
+      // x = omega D^-1 b from the stored 1 / D (finest level: the Jacobi
+      // preconditioner's), a plain stream instead of the stencil pass
+      // that forms D face by face (variable viscosity reads every
+      // coefficient array for it)
+      const T* dv = (l == 0) ? in.dinv : L.dinv;
+      if (!first_done) {
+        if (dv)
+          k_jacobi_first<T><<<vec_blocks(L.g.m_full), kBlock, 0, s>>>(L.g.m_full, om, dv, b, o, st);
+        else
+          face_op<T, kJacobi0>(c, L.op, L.fl, nullptr, b, o, om, nullptr, st);
+      }
       if (hybrid) edge_step<T>(c, L, b, o, st);
       cur = o;
     }
@@ -1106,6 +1126,7 @@ Op<T> make_op(const Grid& g, double eta, const Coef<T>& cf, bool varmu) {
 // Cholesky-based inverse of an SPD matrix (row-major, in place); false if
 // not positive definite
 bool spd_inverse(std::vector<double>& A, int n) {
+  // Cholesky A = L L^T (row-major L; inner products over contiguous rows)
   std::vector<double> L((size_t)n * n, 0.0);
   for (int j = 0; j < n; ++j) {
     const double* Lj = &L[(size_t)j * n];
@@ -1121,27 +1142,35 @@ bool spd_inverse(std::vector<double>& A, int n) {
       L[(size_t)i * n + j] = sum / ljj;
     }
   }
-  // X = L^-1 (lower triangular), by forward substitution on columns
+  // X = L^-1, row by row: row i of L X = e_i gives
+  // X_i = (e_i - sum_{l < i} L[i][l] X_l) / L[i][i], with rows X_l nonzero
+  // in columns 0..l only (contiguous row updates)
   std::vector<double> X((size_t)n * n, 0.0);
   for (int i = 0; i < n; ++i) {
     const double* Li = &L[(size_t)i * n];
     double* Xi = &X[(size_t)i * n];
-    Xi[i] = 1.0 / Li[i];
-    for (int k = 0; k < i; ++k) {
-      // X[i][k] = -(sum_{l=k}^{i-1} L[i][l] X[l][k]) / L[i][i]
-      double sum = 0.0;
-      for (int l = k; l < i; ++l) sum += Li[l] * X[(size_t)l * n + k];
-      Xi[k] = -sum / Li[i];
+    for (int l = 0; l < i; ++l) {
+      const double a = Li[l];
+      const double* Xl = &X[(size_t)l * n];
+      for (int k = 0; k <= l; ++k) Xi[k] -= a * Xl[k];
+    }
+    Xi[i] = 1.0;
+    const double inv = 1.0 / Li[i];
+    for (int k = 0; k <= i; ++k) Xi[k] *= inv;
+  }
+  // A^-1 = X^T X as a sum of outer products of the rows of X (lower part,
+  // then mirrored)
+  for (size_t e = 0; e < (size_t)n * n; ++e) A[e] = 0.0;
+  for (int k = 0; k < n; ++k) {
+    const double* Xk = &X[(size_t)k * n];
+    for (int i = 0; i <= k; ++i) {
+      const double a = Xk[i];
+      double* Ai = &A[(size_t)i * n];
+      for (int j = 0; j <= i; ++j) Ai[j] += a * Xk[j];
     }
   }
-  // A^-1 = X^T X
   for (int i = 0; i < n; ++i)
-    for (int j = 0; j <= i; ++j) {
-      double sum = 0.0;
-      for (int k = i; k < n; ++k) sum += X[(size_t)k * n + i] * X[(size_t)k * n + j];
-      A[(size_t)i * n + j] = sum;
-      A[(size_t)j * n + i] = sum;
-    }
+    for (int j = 0; j < i; ++j) A[(size_t)j * n + i] = A[(size_t)i * n + j];
   return true;
 }
 

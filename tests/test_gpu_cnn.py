@@ -42,6 +42,37 @@ def _ref_forward_bf16(x, params, dim, channels):
     return a
 
 
+def _ref_backward_bf16(x, params, dim, channels, dy):
+    """Reference backward in the GPU's storage precision: the BF16 forward
+    activations (the ReLU masks and the weight-gradient inputs), BF16
+    weights, the gradient seed and every back-propagated hidden gradient
+    rounded to BF16; FP64 sums.  Returns (flat parameter gradient, dx)."""
+    layers = cnn_ref.unflatten(params, dim, channels)
+    offs = cnn_ref.offsets(dim)
+    acts = [bf16(x)]
+    for W, b in layers[:-1]:
+        z = cnn_ref.conv(acts[-1], bf16(W), np.asarray(b, np.float32).astype(np.float64), dim)
+        acts.append(bf16(np.maximum(z, 0.0)))
+    dz = bf16(dy)
+    grads = []
+    for l in range(len(layers) - 1, -1, -1):
+        W = bf16(layers[l][0])
+        a5, dz5 = cnn_ref._as5(acts[l], dim), cnn_ref._as5(dz, dim)
+        cin, cout = W.shape[1], W.shape[2]
+        dW = np.stack([cnn_ref._shift(a5, off, dim).reshape(-1, cin).T @ dz5.reshape(-1, cout)
+                       for off in offs])
+        grads.append((dW, dz5.reshape(-1, cout).sum(0)))
+        da5 = np.zeros(a5.shape)
+        for t, off in enumerate(offs):
+            da5 += cnn_ref._shift(dz5 @ W[t].T, (-off[0], -off[1], -off[2]), dim)
+        da = da5[:, 0] if dim == 2 else da5
+        if l > 0:
+            dz = bf16(da * (acts[l] > 0.0))
+        else:
+            dx = da
+    return np.concatenate([v.reshape(-1) for dW, db in reversed(grads) for v in (dW, db)]), dx
+
+
 CASES = [(2, (3, 16, 16, 16, 2), (2, 24, 40)), (3, (4, 8, 8, 3), (2, 12, 10, 17)),
          (3, (4, 16, 3), (1, 9, 16, 33))]
 
@@ -62,10 +93,12 @@ def test_forward_matches_reference(dim, channels, shape):
     ref = _ref_forward_bf16(x, params, dim, channels)
     err = np.abs(y - ref).max() / np.abs(ref).max()
     err2 = np.linalg.norm(y - ref) / np.linalg.norm(ref)
-    flips = np.mean(np.abs(y - ref) > 1e-5 * np.abs(ref).max())
-    print(f"[case] forward {dim}D {channels}: max {err:.2e} l2 {err2:.2e} "
-          f"fraction above 1e-5: {flips:.2e}", flush=True)
-    assert err <= 1e-2, err
+    print(f"[case] forward {dim}D {channels}: max {err:.2e} l2 {err2:.2e}", flush=True)
+    # the reference stores in BF16 where the GPU does, so only the FP32
+    # accumulation order differs (about sqrt(27 * 16) * 6e-8 per layer), unless
+    # it flips a BF16 rounding of a hidden activation (one BF16 ulp, 4e-3 of
+    # that value): a few such points at most, seen in the max, not the norm
+    assert err2 <= 1e-4 and err <= 1e-2, (err, err2)
     # one layer: only the FP32 accumulation order differs
     one = gk.CNN(dim, (channels[0], channels[1]), seed=5)
     p1 = one.params.astype(np.float64)
@@ -89,12 +122,21 @@ def test_gradients_match_reference(dim, channels, shape):
     dy = cnn_ref.loss_grad(y, e).astype(np.float32)
     g, dx = net.backward(torch.tensor(x, device="cuda"), torch.tensor(dy, device="cuda"))
     gr, dxr = cnn_ref.backward(bf16(x), bf16(params), dim, channels, bf16(dy))
-    # BF16 hidden activations and ReLU masks that flip at the rounding level
-    # make the multi-layer comparison loose; the one-layer check below is tight
+    # against the FP64 oracle (FP64 hidden values): the BF16 storage of the
+    # activations and hidden gradients shows at the percent level
     eg = np.linalg.norm(g - gr) / np.linalg.norm(gr)
     ex = np.linalg.norm(dx.cpu().numpy() - dxr) / np.linalg.norm(dxr)
-    print(f"[case] backward {dim}D {channels}: grad {eg:.2e} dx {ex:.2e}", flush=True)
+    # against the same computation with the GPU's BF16 storage points: only
+    # the FP32 accumulation order differs, and the BF16 roundings of hidden
+    # gradients that it flips (one BF16 ulp each; measured 5e-8 in 2D, 6e-6
+    # and 9e-5 in 3D)
+    ge, dxe = _ref_backward_bf16(x, params, dim, channels, dy)
+    eg2 = np.linalg.norm(g - ge) / np.linalg.norm(ge)
+    ex2 = np.linalg.norm(dx.cpu().numpy() - dxe) / np.linalg.norm(dxe)
+    print(f"[case] backward {dim}D {channels}: vs FP64 grad {eg:.2e} dx {ex:.2e}; "
+          f"vs BF16 storage grad {eg2:.2e} dx {ex2:.2e}", flush=True)
     assert eg <= 2e-2 and ex <= 6e-2, (eg, ex)
+    assert eg2 <= 1e-4 and ex2 <= 2e-4, (eg2, ex2)
     # per layer: weight and bias blocks each agree
     o = 0
     taps = 9 if dim == 2 else 27

@@ -45,12 +45,17 @@ def _mu(g, on):
     return np.exp(np.random.default_rng(5).standard_normal(g.n_cells)) if on else None
 
 
+@pytest.mark.parametrize("transfer", ["div", "smooth"])
 @pytest.mark.parametrize("smoother", ["jacobi", "hybrid"])
 @pytest.mark.parametrize("name,grid,eta,varmu", MG_CASES, ids=[c[0] for c in MG_CASES])
-def test_vcycle_symmetric_positive(name, grid, eta, varmu, smoother):
-    _say("vcycle sym", name, smoother)
+def test_vcycle_symmetric_positive(name, grid, eta, varmu, smoother, transfer):
+    """x.V(y) = y.V(x) and x.V(x) > 0 for both smoothers and both transfer
+    pairs (restriction = prolongation^T / 2^d in each)."""
+    _say("vcycle sym", name, smoother, transfer)
     gk = _gk()
-    s = gk.Solver(grid, _mu(grid, varmu), eta, inner="mg", smoother=smoother)
+    s = gk.Solver(grid, _mu(grid, varmu), eta, inner="mg", smoother=smoother,
+                  mg_transfer=transfer)
+    assert s.stats()["mg_transfer"] == transfer
     x = _dev(P.random_vector(grid, 1))
     y = _dev(P.random_vector(grid, 2))
     Vx = s.precondition(x)
