@@ -431,7 +431,7 @@ def study_learned(gk, torch, problems, dim, train_seeds, eval_seeds, steps=1500)
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--steps", type=int, default=15)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", default="mixed_learned", choices=list(MODES))
     ap.add_argument("--n", type=int, default=128, help="cells per axis of the 3D problem")
