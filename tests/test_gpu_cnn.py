@@ -302,6 +302,46 @@ def test_learned_fcg_with_network_on_to_convergence():
     assert 0.0 < il["learned_gain"] < float("inf")
 
 
+@pytest.mark.skip(reason="no trained network reduces the inner iterations below MG-PCG's on "
+                  "these workloads: flexible CG with the network kept on needs 1359.8 "
+                  "against 113.4 per solve (32^3 lid, Jacobi V-cycle), FGMRES 76.2 against "
+                  "46.8 (hybrid V-cycle), C4 2D 103.2 against 51.8; the network removes "
+                  "about 1 % of the error energy the V-cycle step removes (measured in the "
+                  "tests above and by bench.py --study learned2d / learned3d)")
+def test_learned_network_reduces_inner_iterations():
+    """The goal the learned preconditioner was built for: with the network in
+    every direction (guards off), fewer inner iterations per solve than
+    MG-PCG on a held-out forcing, with the oracle's FP64 residual <= 1e-8.
+    Kept, skipped, as the statement of what is not reached."""
+    import torch
+    from paper_2001_10424_amd.cnn import capture_pairs
+    gk = _gk()
+    hyb = dict(smoother="hybrid", nu_pre=1, nu_post=1, inner_maxit=20000)
+    ins, tgs = [], []
+    for seed in (131, 132, 133, 134):
+        pr = _small_problem(seed, n=32)
+        s = _solver(gk, pr, inner="mg", **hyb)
+        a, b = capture_pairs(s, _dev(pr.g), _dev(pr.r), tol=1e-4, max_pairs=24)
+        ins.append(a)
+        tgs.append(b)
+        s.close()
+    inputs, targets = torch.cat(ins).contiguous(), torch.cat(tgs).contiguous()
+    net = gk.CNN(3, (4, 8, 8, 3), seed=0)
+    net.train(inputs, targets, (32, 32, 32), crop=16, batch=8, steps=400, lr=1e-3, seed=1)
+    pr = _small_problem(19, n=32)
+    per_solve = {}
+    for inner in ("mg", "learned"):
+        s = _solver(gk, pr, inner=inner, learned_min_gain=-1.0, **hyb)
+        if inner == "learned":
+            s.attach_cnn(net)
+        w, p, info = s.solve(_dev(pr.g), _dev(pr.r), tol=1e-4)
+        s.close()
+        _, _, nr = oracle.saddle_residual(pr.grid, pr.g, pr.r, w.cpu().numpy(), p.cpu().numpy())
+        assert nr[0] <= 1e-8 * nr[3]
+        per_solve[inner] = info["inner_iterations"] / info["inner_solves"]
+    assert per_solve["learned"] < per_solve["mg"], per_solve
+
+
 def test_learned_preconditioner_in_fgmres():
     """The network correction inside FGMRES, which orthogonalises against the
     whole cycle and takes a preconditioner that changes from step to step:
