@@ -27,7 +27,9 @@
  * synchronous: the calls that read device buffers (forward, backward, train,
  * eval) first wait for all work already submitted to the device, so buffers
  * written on any stream are complete, and return when their own work is
- * done.  Errors as in gkb.h (GKB_EINVAL, GKB_ENOMEM, GKB_EHIP).
+ * done.  Errors as in gkb.h (GKB_EINVAL, GKB_ENOMEM, GKB_EHIP); a call (or
+ * an attach) whose points (batch * nx * ny * nz) exceed 2^31 - 1 returns
+ * GKB_EINVAL.
  */
 #ifndef GKB_CNN_H
 #define GKB_CNN_H

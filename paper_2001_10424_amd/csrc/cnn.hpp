@@ -56,13 +56,25 @@ __device__ __forceinline__ long nb_index(const CnnGeom& g, long p, int i, int j,
   return p + dx + (long)dy * g.nx + (long)dz * g.nx * g.ny;
 }
 
+// coordinates of point p in its grid, in 32-bit arithmetic (every network
+// call keeps batch * points below 2^31)
 __device__ __forceinline__ void coords(const CnnGeom& g, long p, int& i, int& j, int& k) {
-  i = int(p % g.nx);
-  j = int((p / g.nx) % g.ny);
-  k = int((p / ((long)g.nx * g.ny)) % g.nz);
+  const unsigned q = unsigned(p), nx = unsigned(g.nx), ny = unsigned(g.ny);
+  const unsigned r = q / nx, s = r / ny;
+  i = int(q - r * nx);
+  j = int(r - s * ny);
+  k = int(s % unsigned(g.nz));
 }
 
 enum ConvOut { kOutReluBf16 = 0, kOutF32 = 1, kOutMaskBf16 = 2 };
+
+// Blocks for a convolution over P points: each block stages the layer's
+// weights in LDS once and then takes groups of 64 points (16 per wave) in a
+// grid-stride loop, so the weight staging is paid per block, not per group.
+inline int conv_blocks(long P) {
+  const long groups = (P + 63) / 64;
+  return int(groups < 2048 ? groups : 2048);
+}
 
 // out[p][n] = bias[n] + sum_tap sum_c in[p + off(tap)][c] * w[tap][n][c]
 template <int DIM, int OUT>
@@ -79,41 +91,43 @@ __global__ __launch_bounds__(256) void k_conv(CnnGeom g, const uint16_t* __restr
   for (int e = threadIdx.x; e < TAPS * 256; e += 256) sw[e] = w[e];
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const long p0 = ((long)blockIdx.x * 4 + wv) * 16;
-  if (p0 >= g.P) return;
   const int m = lane & 15, kg = lane >> 4;
-  const long p = p0 + m;
-  const bool valid = p < g.P;
-  int i = 0, j = 0, k = 0;
-  if (valid) coords(g, p, i, j, k);
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (long base = (long)blockIdx.x * 64; base < g.P; base += (long)gridDim.x * 64) {
+    const long p0 = base + wv * 16;
+    if (p0 >= g.P) break;
+    const long p = p0 + m;
+    const bool valid = p < g.P;
+    int i = 0, j = 0, k = 0;
+    if (valid) coords(g, p, i, j, k);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int t = 0; t < TAPS; ++t) {
-    int dx, dy, dz;
-    tap_off(t, DIM, dx, dy, dz);
-    bf16x4 a = {0, 0, 0, 0};
-    if (valid) {
-      const long q = nb_index(g, p, i, j, k, dx, dy, dz);
-      if (q >= 0) a = *reinterpret_cast<const bf16x4*>(in + q * kCP + 4 * kg);
+    for (int t = 0; t < TAPS; ++t) {
+      int dx, dy, dz;
+      tap_off(t, DIM, dx, dy, dz);
+      bf16x4 a = {0, 0, 0, 0};
+      if (valid) {
+        const long q = nb_index(g, p, i, j, k, dx, dy, dz);
+        if (q >= 0) a = *reinterpret_cast<const bf16x4*>(in + q * kCP + 4 * kg);
+      }
+      const bf16x4 b = *reinterpret_cast<const bf16x4*>(sw + t * 256 + m * 16 + 4 * kg);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
     }
-    const bf16x4 b = *reinterpret_cast<const bf16x4*>(sw + t * 256 + m * 16 + 4 * kg);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-  }
-  // acc[q] = D[row 4kg+q][col m]: point p0 + 4kg + q, channel m
-  const float bm = bias ? bias[m] : 0.f;
+    // acc[q] = D[row 4kg+q][col m]: point p0 + 4kg + q, channel m
+    const float bm = bias ? bias[m] : 0.f;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const long pq = p0 + 4 * kg + q;
-    if (pq >= g.P) continue;
-    float v = acc[q] + bm;
-    if (OUT == kOutReluBf16) {
-      static_cast<uint16_t*>(out)[pq * kCP + m] = f2bf(v > 0.f ? v : 0.f);
-    } else if (OUT == kOutF32) {
-      static_cast<float*>(out)[pq * kCP + m] = v;
-    } else {
-      const uint16_t h = mask[pq * kCP + m];
-      const bool pos = h != 0 && (h & 0x8000u) == 0;
-      static_cast<uint16_t*>(out)[pq * kCP + m] = f2bf(pos ? v : 0.f);
+    for (int q = 0; q < 4; ++q) {
+      const long pq = p0 + 4 * kg + q;
+      if (pq >= g.P) continue;
+      float v = acc[q] + bm;
+      if (OUT == kOutReluBf16) {
+        static_cast<uint16_t*>(out)[pq * kCP + m] = f2bf(v > 0.f ? v : 0.f);
+      } else if (OUT == kOutF32) {
+        static_cast<float*>(out)[pq * kCP + m] = v;
+      } else {
+        const uint16_t h = mask[pq * kCP + m];
+        const bool pos = h != 0 && (h & 0x8000u) == 0;
+        static_cast<uint16_t*>(out)[pq * kCP + m] = f2bf(pos ? v : 0.f);
+      }
     }
   }
 }
@@ -428,6 +442,8 @@ int cnn_prepare_weights(gkb_cnn* n) {
 }
 
 int cnn_reserve(gkb_cnn* n, long P) {
+  // point indices are decomposed in 32-bit arithmetic (coords)
+  if (P <= 0 || P > 0x7fffffffL) return GKB_EINVAL;
   if (P <= n->cap) return GKB_OK;
   for (int l = 0; l < n->L; ++l) {
     if (n->act[l]) (void)hipFree(n->act[l]);
@@ -445,7 +461,7 @@ int cnn_reserve(gkb_cnn* n, long P) {
 
 template <int DIM>
 void cnn_forward_dim(gkb_cnn* n, const gkb::CnnGeom& g) {
-  const int blocks = (int)((g.P + 63) / 64);
+  const int blocks = gkb::conv_blocks(g.P);
   for (int l = 0; l < n->L; ++l) {
     const uint16_t* w = n->wf + (size_t)l * n->taps * 256;
     const float* b = n->bias + 16 * l;
@@ -478,7 +494,7 @@ int cnn_backward_dim(gkb_cnn* n, const gkb::CnnGeom& g, float* dx16) {
     CNNCK(hipMalloc(&n->wpart, (size_t)wblk * NP * sizeof(float)));
     n->wblk = wblk;
   }
-  const int blocks = (int)((g.P + 63) / 64);
+  const int blocks = gkb::conv_blocks(g.P);
   uint16_t* dz = n->dz0;
   uint16_t* dzn = n->dz1;
   for (int l = n->L - 1; l >= 0; --l) {

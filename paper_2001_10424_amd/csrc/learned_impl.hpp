@@ -345,7 +345,7 @@ void learned_apply(gkb_ctx* c, Inner<T>& in, const T* r_in, T* z_out, const PcgS
   else
     k_pack_faces<T, 3><<<nb, 256, 0, s>>>(G, rt, st, double(L->m_unknown), L->logmu, net->act[0]);
   CnnGeom g{G.n[0], G.n[1], G.n[2], 1, (long)G.n_cells};
-  const int blocks = (int)((g.P + 63) / 64);
+  const int blocks = conv_blocks(g.P);
   const int* f1 = &st->done;
   const int* f2 = &st->fallback;
   for (int l = 0; l < net->L; ++l) {
