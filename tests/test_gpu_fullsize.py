@@ -27,25 +27,27 @@ def _gk():
     return gk
 
 
-# (precision, inner, per-sweep lower-bound tolerance, inner tolerance, delay)
-# as timed by bench.py
-BENCH_MODES = {
-    "fp64_mg": dict(precision="fp64", inner="mg", inner_tol=1e-3, tol=1e-2, delay=2),
-    "mixed_mg": dict(precision="mixed", inner="mg", inner_tol=3e-4, tol=1e-2, delay=2),
-    "fp64_gkb1": dict(precision="fp64", inner="mg", inner_tol=1e-10, tol=1e-9, delay=5),
-    "fp64_mg_hybrid": dict(precision="fp64", inner="mg", inner_tol=3e-4, tol=3e-3, delay=2,
-                           smoother="hybrid", nu_pre=1, nu_post=1),
-    "mixed_mg_hybrid": dict(precision="mixed", inner="mg", inner_tol=3e-4, tol=3e-3, delay=2,
-                            smoother="hybrid", nu_pre=1, nu_post=1),
-}
+def _bench_modes():
+    """The timed MG modes with the settings bench.py times them with
+    (precision, inner, per-sweep lower-bound tolerance, inner tolerance,
+    delay, smoother, sweeps)."""
+    import bench  # the repository root is on sys.path (tests/conftest.py)
+    out = {}
+    for mode in ("fp64_mg", "mixed_mg", "fp64_gkb1", "fp64_mg_hybrid", "mixed_mg_hybrid"):
+        prec, inner, tol, itol, delay, smoother, nu = bench.MODES[mode]
+        out[mode] = dict(precision=prec, inner=inner, inner_tol=itol, tol=tol, delay=delay,
+                         smoother=smoother, nu_pre=nu, nu_post=nu)
+    return out
+
+
+BENCH_MODES = _bench_modes()
 
 
 def _solve(pr, mode):
     gk = _gk()
     m = dict(BENCH_MODES[mode])
     tol, delay = m.pop("tol"), m.pop("delay")
-    kw = dict(nu_pre=2, nu_post=2, inner_maxit=5000, maxit=200, refine_tol=1e-8, max_sweeps=12,
-              check_every=8)
+    kw = dict(inner_maxit=5000, maxit=200, refine_tol=1e-8, max_sweeps=30, check_every=8)
     kw.update(m)
     s = gk.Solver(pr.grid, pr.mu, pr.eta, **kw)
     w, p, info = s.solve(_dev(pr.g), _dev(pr.r), tol=tol, delay=delay)
