@@ -71,9 +71,13 @@ enum ConvOut { kOutReluBf16 = 0, kOutF32 = 1, kOutMaskBf16 = 2 };
 // Blocks for a convolution over P points: each block stages the layer's
 // weights in LDS once and then takes groups of 64 points (16 per wave) in a
 // grid-stride loop, so the weight staging is paid per block, not per group.
+// At most 8192 blocks: a 64^3 x 2 training batch keeps one group per block
+// (a 2048-block cap, four groups per block, made its gradient layers 25 %
+// slower: each wave waits on its loads group after group), and a 128^3
+// inference pass takes four groups per block.
 inline int conv_blocks(long P) {
   const long groups = (P + 63) / 64;
-  return int(groups < 2048 ? groups : 2048);
+  return int(groups < 8192 ? groups : 8192);
 }
 
 // out[p][n] = bias[n] + sum_tap sum_c in[p + off(tap)][c] * w[tap][n][c]

@@ -271,7 +271,11 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
   // faces at (i/2, j/2) (w shares v's: both arrays are nx/2 wide) and six
   // bits: odd i, odd j, coarse u faces I and I+1 unknown, coarse v faces J
   // and J+1 unknown.  The coarse values (faces I / I+1, J / J+1, coarse
-  // planes K / K+1) are prefetched with the plane.
+  // planes K / K+1) are prefetched with the plane; an odd plane k >= k0
+  // lies on the coarse plane K of the even plane before it, staged just
+  // before it by the same thread, and takes that plane's five values from
+  // registers (only the plane K+1 of its w faces is loaded), which halves
+  // the coarse loads.
   constexpr bool kP = MODE == kJacobiP;
   // kApplyDotP: the staged values are p' = z + beta p (x = z, b = p); p is
   // loaded with z into the second register set, p' is written to y2 at the
@@ -307,6 +311,10 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
     T v[3][kPer];
     T c[kPC][kPer];  // kJacobiP: coarse u(I), u(I+1), v(J), v(J+1), w(K), w(K+1)
   };
+  // kJacobiP: an odd plane after the block's first takes the coarse plane-K
+  // values of the even plane staged before it (cprev)
+  auto reuse_coarse = [&](int k) { return (k & 1) && k >= k0 && k < nz; };
+  T cprev[5][kPer];
   auto fetch_plane = [&](int k, FRegs& F) {
     const int kk = min(max(k, 0), nz - 1);
 #pragma unroll
@@ -330,13 +338,15 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
       const unsigned sw = unsigned(K * Gc.ext[2][0] * Gc.ext[2][1]) * E + dwc;
       const unsigned sw1 = unsigned(K1 * Gc.ext[2][0] * Gc.ext[2][1]) * E + dwc;
       const unsigned rowv = unsigned(Gc.ext[1][0]) * E;
+      if (!reuse_coarse(k)) {  // uniform
 #pragma unroll
-      for (int q = 0; q < kPer; ++q) {
-        F.c[0][q] = buf_load<T>(rc, pcu[q], su);
-        F.c[1][q] = buf_load<T>(rc, pcu[q] + E, su);
-        F.c[2][q] = buf_load<T>(rc, pcv[q], sv);
-        F.c[3][q] = buf_load<T>(rc, pcv[q] + rowv, sv);
-        F.c[4][q] = buf_load<T>(rc, pcv[q], sw);
+        for (int q = 0; q < kPer; ++q) {
+          F.c[0][q] = buf_load<T>(rc, pcu[q], su);
+          F.c[1][q] = buf_load<T>(rc, pcu[q] + E, su);
+          F.c[2][q] = buf_load<T>(rc, pcv[q], sv);
+          F.c[3][q] = buf_load<T>(rc, pcv[q] + rowv, sv);
+          F.c[4][q] = buf_load<T>(rc, pcv[q], sw);
+        }
       }
       // the coarse plane above is needed by the w faces of odd planes only
       if (kk & 1) {
@@ -391,12 +401,19 @@ __global__ __launch_bounds__(256, kTileMinWaves<T>) void k_tile3d(Op<T> op, cons
       const bool wK = !((K == 0 && Gc.bc[4] == kDir) || (K == Gc.n[2] && Gc.bc[5] == kDir));
       const bool wK1 = !(K + 1 == Gc.n[2] && Gc.bc[5] == kDir);
       const bool oddk = k & 1;
+      const bool reuse = reuse_coarse(k);  // uniform
 #pragma unroll
       for (int q = 0; q < kPer; ++q) {
+        T cv[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          cv[c] = reuse ? cprev[c][q] : F.c[c][q];
+          cprev[c][q] = cv[c];
+        }
         const unsigned bq = pbits >> (6 * q);
-        const T u0 = (bq & 4u) ? F.c[0][q] : T(0), u1 = (bq & 8u) ? F.c[1][q] : T(0);
-        const T v0 = (bq & 16u) ? F.c[2][q] : T(0), v1 = (bq & 32u) ? F.c[3][q] : T(0);
-        const T w0 = wK ? F.c[4][q] : T(0), w1 = wK1 ? F.c[5][q] : T(0);
+        const T u0 = (bq & 4u) ? cv[0] : T(0), u1 = (bq & 8u) ? cv[1] : T(0);
+        const T v0 = (bq & 16u) ? cv[2] : T(0), v1 = (bq & 32u) ? cv[3] : T(0);
+        const T w0 = wK ? cv[4] : T(0), w1 = wK1 ? F.c[5][q] : T(0);
         val[0][q] += (bq & 1u) ? T(0.5) * (u0 + u1) : u0;
         val[1][q] += (bq & 2u) ? T(0.5) * (v0 + v1) : v0;
         val[2][q] += oddk ? T(0.5) * (w0 + w1) : w0;
