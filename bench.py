@@ -399,7 +399,8 @@ def study_learned(gk, torch, problems, dim, train_seeds, eval_seeds, steps=1500)
     training forcings, the network is trained on the GPU, and the held-out
     forcings are solved to the FP64 residual 1e-8 by FP64 MG-PCG, FP32
     MG-PCG and FP32 learned flexible CG (default guards, and with the network
-    kept on).  One JSON line per solve, then a summary line."""
+    kept on), with the per-sweep setting of the timed hybrid modes.  One JSON
+    line per solve, then a summary line."""
     from paper_2001_10424_amd.cnn import capture_pairs
     n, mu_seed = (256, 7) if dim == 2 else (192, 8)
     channels = (3, 16, 16, 16, 2) if dim == 2 else CNN_CHANNELS
@@ -453,6 +454,7 @@ def study_learned(gk, torch, problems, dim, train_seeds, eval_seeds, steps=1500)
         # an inner solve that needs more than 2000 iterations ends the solve
         # (reported as an error line)
         modes["mixed_learned_on"]["inner_maxit"] = 2000
+    tol, delay = MODES["mixed_mg_hybrid"][2], MODES["mixed_mg_hybrid"][4]
     summary = {}
     for sd in eval_seeds:
         pr = problems.stokes_problem(dim, n, seed=sd, eta=1e3, mu_seed=mu_seed)
@@ -465,9 +467,9 @@ def study_learned(gk, torch, problems, dim, train_seeds, eval_seeds, steps=1500)
             if opts["inner"] == "learned":
                 s.attach_cnn(net)
             try:
-                s.solve(g, r, tol=3e-3, delay=2)
+                s.solve(g, r, tol=tol, delay=delay)
                 log(f"[study] seed {sd}: {name} warm-up solve done")
-                dt, w, p, info = timed_solve(torch, s, g, r, 3e-3, 2)
+                dt, w, p, info = timed_solve(torch, s, g, r, tol, delay)
             except RuntimeError as e:  # reported, the study goes on
                 s.close()
                 print(json.dumps(dict(mode=name, seed=sd, error=str(e))), flush=True)
@@ -563,8 +565,9 @@ def main():
                               "smooth_avg_ms": ms, "bytes_per_launch": nbytes}))
             s.close()
             return
-        s.solve(g, r, tol=3e-3, delay=2)
-        dt, w, p, info = timed_solve(torch, s, g, r, 3e-3, 2)
+        tol, delay = MODES["mixed_mg_hybrid"][2], MODES["mixed_mg_hybrid"][4]
+        s.solve(g, r, tol=tol, delay=delay)
+        dt, w, p, info = timed_solve(torch, s, g, r, tol, delay)
         norms, _, _ = s.residual(g, r, w, p)
         ms = s.time_kernel("smooth", 20)
         print(json.dumps({"workload": "varvisc3d_192", "solve_s": round(dt, 4),

@@ -184,14 +184,16 @@ def test_varvisc_full_size_solve_hybrid(dim, n, mu_seed):
     """The variable-viscosity workloads (log-normal mu, contrast 1e3, eta =
     1e3) at full size with FP32 inner MG-PCG on the hybrid face + edge
     smoother (point-Jacobi multigrid needs thousands of iterations per inner
-    solve here): FP64 residual <= 1e-8 by the oracle."""
+    solve here), with the per-sweep setting of the timed hybrid mode: FP64
+    residual <= 1e-8 by the oracle."""
     _say("varvisc full solve hybrid", dim, n)
     gk = _gk()
+    m = BENCH_MODES["mixed_mg_hybrid"]
     pr = P.stokes_problem(dim, n, seed=10000, eta=1e3, mu_seed=mu_seed)
     s = gk.Solver(pr.grid, pr.mu, pr.eta, precision="mixed", inner="mg", smoother="hybrid",
-                  nu_pre=1, nu_post=1, inner_tol=3e-4, inner_maxit=20000, maxit=200,
+                  nu_pre=1, nu_post=1, inner_tol=m["inner_tol"], inner_maxit=20000, maxit=200,
                   refine_tol=1e-8, max_sweeps=30)
-    w, p, info = s.solve(_dev(pr.g), _dev(pr.r), tol=3e-3, delay=2)
+    w, p, info = s.solve(_dev(pr.g), _dev(pr.r), tol=m["tol"], delay=m["delay"])
     print("[case] sweeps", info["sweeps"], "K", info["outer_iterations"], "inner",
           info["inner_iterations"], flush=True)
     _, _, nr = oracle.saddle_residual(pr.grid, pr.g, pr.r, w.cpu().numpy(), p.cpu().numpy(),
