@@ -2,7 +2,10 @@
 //
 // Convolutions are implicit GEMMs on v_mfma_f32_16x16x16_bf16: a wave64
 // computes 16 output points x 16 output channels; the GEMM K dimension runs
-// over the taps, each tap contributing one 16 (input channels) deep MFMA.
+// over taps x input channels, 16 deep per MFMA: one tap of 16 channels, two
+// taps of 8 or four taps of 4 (a layer reads only the channel group its
+// input fills, so 8- and 4-channel inputs take 2x and 4x fewer MFMAs and
+// gathered bytes).
 // Activations are channels-last BF16 padded to 16 channels (32 bytes per
 // point), so the A fragment of a lane (4 consecutive channels of one point)
 // is one 8-byte load; the 3x3(x3) weights of a layer sit in LDS in the
@@ -80,8 +83,9 @@ inline int conv_blocks(long P) {
   return int(groups < 8192 ? groups : 8192);
 }
 
-// out[p][n] = bias[n] + sum_tap sum_c in[p + off(tap)][c] * w[tap][n][c]
-template <int DIM, int OUT>
+// out[p][n] = bias[n] + sum_tap sum_c in[p + off(tap)][c] * w[tap][n][c],
+// the input channels c < CG (16, 8 or 4; the padded channels above are zero)
+template <int DIM, int OUT, int CG = kCP>
 __global__ __launch_bounds__(256) void k_conv(CnnGeom g, const uint16_t* __restrict__ in,
                                               const uint16_t* __restrict__ w,
                                               const float* __restrict__ bias, void* __restrict__ out,
@@ -89,6 +93,8 @@ __global__ __launch_bounds__(256) void k_conv(CnnGeom g, const uint16_t* __restr
                                               const int* __restrict__ skip1 = nullptr,
                                               const int* __restrict__ skip2 = nullptr) {
   constexpr int TAPS = DIM == 2 ? 9 : 27;
+  static_assert(CG == 16 || CG == 8 || CG == 4, "channel group");
+  constexpr int TPM = kCP / CG;  // taps per MFMA
   // device-side switches (solve converged / learned correction disabled)
   if ((skip1 && *skip1) || (skip2 && *skip2)) return;
   __shared__ uint16_t sw[TAPS * 256];
@@ -96,6 +102,9 @@ __global__ __launch_bounds__(256) void k_conv(CnnGeom g, const uint16_t* __restr
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int m = lane & 15, kg = lane >> 4;
+  // the lane's four K values: tap t + tsub, channels c0 .. c0 + 3
+  const int tsub = CG == 16 ? 0 : (CG == 8 ? kg >> 1 : kg);
+  const int c0 = CG == 16 ? 4 * kg : (CG == 8 ? 4 * (kg & 1) : 0);
   for (long base = (long)blockIdx.x * 64; base < g.P; base += (long)gridDim.x * 64) {
     const long p0 = base + wv * 16;
     if (p0 >= g.P) break;
@@ -105,15 +114,18 @@ __global__ __launch_bounds__(256) void k_conv(CnnGeom g, const uint16_t* __restr
     if (valid) coords(g, p, i, j, k);
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int t = 0; t < TAPS; ++t) {
+    for (int t0 = 0; t0 < TAPS; t0 += TPM) {
+      const int t = t0 + tsub;
       int dx, dy, dz;
       tap_off(t, DIM, dx, dy, dz);
-      bf16x4 a = {0, 0, 0, 0};
-      if (valid) {
-        const long q = nb_index(g, p, i, j, k, dx, dy, dz);
-        if (q >= 0) a = *reinterpret_cast<const bf16x4*>(in + q * kCP + 4 * kg);
+      bf16x4 a = {0, 0, 0, 0}, b = {0, 0, 0, 0};
+      if (t < TAPS) {  // the last group of a layer may run past the taps
+        if (valid) {
+          const long q = nb_index(g, p, i, j, k, dx, dy, dz);
+          if (q >= 0) a = *reinterpret_cast<const bf16x4*>(in + q * kCP + c0);
+        }
+        b = *reinterpret_cast<const bf16x4*>(sw + t * 256 + m * 16 + c0);
       }
-      const bf16x4 b = *reinterpret_cast<const bf16x4*>(sw + t * 256 + m * 16 + 4 * kg);
       acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
     }
     // acc[q] = D[row 4kg+q][col m]: point p0 + 4kg + q, channel m
@@ -136,22 +148,43 @@ __global__ __launch_bounds__(256) void k_conv(CnnGeom g, const uint16_t* __restr
   }
 }
 
+// Launch k_conv with the smallest channel group that holds the input's
+// cin channels.
+template <int DIM, int OUT>
+void launch_conv(int cin, int blocks, hipStream_t s, const CnnGeom& g, const uint16_t* in,
+                 const uint16_t* w, const float* bias, void* out, const uint16_t* mask,
+                 const int* skip1 = nullptr, const int* skip2 = nullptr) {
+  if (cin <= 4)
+    k_conv<DIM, OUT, 4><<<blocks, 256, 0, s>>>(g, in, w, bias, out, mask, skip1, skip2);
+  else if (cin <= 8)
+    k_conv<DIM, OUT, 8><<<blocks, 256, 0, s>>>(g, in, w, bias, out, mask, skip1, skip2);
+  else
+    k_conv<DIM, OUT, 16><<<blocks, 256, 0, s>>>(g, in, w, bias, out, mask, skip1, skip2);
+}
+
 // Weight / bias gradient partials of one layer: for every tap
 //   dW[tap][ci][co] = sum_p act[p + off(tap)][ci] * dz[p][co],  db[co] = sum_p dz[p][co]
 // Each block covers a strided set of 16-point chunks and writes TAPS*256+16
-// FP32 partials.
-template <int DIM>
+// FP32 partials.  The 16 rows of an MFMA tile are (tap, ci) pairs: one tap
+// of 16 input channels, two taps of 8 or four of 4 (CG), so a layer with
+// few input channels needs fewer tiles.
+template <int DIM, int CG = kCP>
 __global__ __launch_bounds__(256) void k_wgrad(CnnGeom g, const uint16_t* __restrict__ act,
                                                const uint16_t* __restrict__ dz,
                                                float* __restrict__ part) {
   constexpr int TAPS = DIM == 2 ? 9 : 27;
   constexpr int NP = TAPS * 256 + 16;
+  static_assert(CG == 16 || CG == 8 || CG == 4, "channel group");
+  constexpr int TPM = kCP / CG;                 // taps per tile
+  constexpr int NT = (TAPS + TPM - 1) / TPM;    // tiles
   __shared__ float red[NP];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int m = lane & 15, kg = lane >> 4;
-  f32x4 acc[TAPS];
+  // the lane's A row m: tap t * TPM + msub, input channel mc
+  const int msub = m / CG, mc = m % CG;
+  f32x4 acc[NT];
 #pragma unroll
-  for (int t = 0; t < TAPS; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
   float db = 0.f;
   const long nchunks = (g.P + 15) / 16;
   const long nw = (long)gridDim.x * 4;
@@ -173,16 +206,17 @@ __global__ __launch_bounds__(256) void k_wgrad(CnnGeom g, const uint16_t* __rest
       db += bf2f((uint16_t)b[q]);
     }
 #pragma unroll
-    for (int t = 0; t < TAPS; ++t) {
+    for (int t = 0; t < NT; ++t) {
+      const int tap = t * TPM + msub;
       int dx, dy, dzz;
-      tap_off(t, DIM, dx, dy, dzz);
+      tap_off(tap, DIM, dx, dy, dzz);
       bf16x4 a;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         a[q] = 0;
-        if (pq[q] < g.P) {
+        if (tap < TAPS && pq[q] < g.P) {
           const long n = nb_index(g, pq[q], ci[q], cj[q], ck[q], dx, dy, dzz);
-          if (n >= 0) a[q] = (short)act[n * kCP + m];
+          if (n >= 0) a[q] = (short)act[n * kCP + mc];
         }
       }
       acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
@@ -192,14 +226,18 @@ __global__ __launch_bounds__(256) void k_wgrad(CnnGeom g, const uint16_t* __rest
   for (int e = threadIdx.x; e < NP; e += 256) red[e] = 0.f;
   dbs[threadIdx.x] = db;  // slot (wave, kg, m)
   __syncthreads();
-  // waves add their tiles in a fixed order: D[ci = 4kg+q][co = m]; every
-  // barrier below is reached by all waves
+  // waves add their tiles in a fixed order: D[row 4kg+q][co = m], row =
+  // (tap t * TPM + row / CG, ci = row % CG); every barrier below is reached
+  // by all waves
   for (int w = 0; w < 4; ++w) {
     if (wv == w) {
 #pragma unroll
-      for (int t = 0; t < TAPS; ++t)
+      for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) red[t * 256 + (4 * kg + q) * 16 + m] += acc[t][q];
+        for (int q = 0; q < 4; ++q) {
+          const int row = 4 * kg + q, tap = t * TPM + row / CG;
+          if (tap < TAPS) red[tap * 256 + (row % CG) * 16 + m] += acc[t][q];
+        }
     }
     __syncthreads();
   }
@@ -470,11 +508,11 @@ void cnn_forward_dim(gkb_cnn* n, const gkb::CnnGeom& g) {
     const uint16_t* w = n->wf + (size_t)l * n->taps * 256;
     const float* b = n->bias + 16 * l;
     if (l < n->L - 1)
-      gkb::k_conv<DIM, gkb::kOutReluBf16><<<blocks, 256, 0, n->s>>>(g, n->act[l], w, b,
-                                                                    n->act[l + 1], nullptr);
+      gkb::launch_conv<DIM, gkb::kOutReluBf16>(n->ch[l], blocks, n->s, g, n->act[l], w, b,
+                                               n->act[l + 1], nullptr);
     else
-      gkb::k_conv<DIM, gkb::kOutF32><<<blocks, 256, 0, n->s>>>(g, n->act[l], w, b, n->y16,
-                                                               nullptr);
+      gkb::launch_conv<DIM, gkb::kOutF32>(n->ch[l], blocks, n->s, g, n->act[l], w, b, n->y16,
+                                          nullptr);
   }
 }
 
@@ -502,17 +540,24 @@ int cnn_backward_dim(gkb_cnn* n, const gkb::CnnGeom& g, float* dx16) {
   uint16_t* dz = n->dz0;
   uint16_t* dzn = n->dz1;
   for (int l = n->L - 1; l >= 0; --l) {
-    gkb::k_wgrad<DIM><<<wblk, 256, 0, n->s>>>(g, n->act[l], dz, n->wpart);
+    if (n->ch[l] <= 4)
+      gkb::k_wgrad<DIM, 4><<<wblk, 256, 0, n->s>>>(g, n->act[l], dz, n->wpart);
+    else if (n->ch[l] <= 8)
+      gkb::k_wgrad<DIM, 8><<<wblk, 256, 0, n->s>>>(g, n->act[l], dz, n->wpart);
+    else
+      gkb::k_wgrad<DIM, 16><<<wblk, 256, 0, n->s>>>(g, n->act[l], dz, n->wpart);
     gkb::k_wgrad_reduce<<<(NP + 255) / 256, 256, 0, n->s>>>(n->wpart, wblk, NP, n->pad);
     gkb::k_grad_flat<<<cnn_grid(TAPS * 256 + 16), 256, 0, n->s>>>(n->pad, TAPS, n->ch[l],
                                                                    n->ch[l + 1], n->grad + n->off[l]);
     const uint16_t* wd = n->wd + (size_t)l * TAPS * 256;
+    // the adjoint convolution reads the layer's output channels
     if (l > 0) {
-      gkb::k_conv<DIM, gkb::kOutMaskBf16><<<blocks, 256, 0, n->s>>>(g, dz, wd, nullptr, dzn,
-                                                                     n->act[l]);
+      gkb::launch_conv<DIM, gkb::kOutMaskBf16>(n->ch[l + 1], blocks, n->s, g, dz, wd, nullptr,
+                                               dzn, n->act[l]);
       std::swap(dz, dzn);
     } else if (dx16) {
-      gkb::k_conv<DIM, gkb::kOutF32><<<blocks, 256, 0, n->s>>>(g, dz, wd, nullptr, dx16, nullptr);
+      gkb::launch_conv<DIM, gkb::kOutF32>(n->ch[l + 1], blocks, n->s, g, dz, wd, nullptr, dx16,
+                                          nullptr);
     }
   }
   CNNCK(hipGetLastError());

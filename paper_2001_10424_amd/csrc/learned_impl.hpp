@@ -351,16 +351,17 @@ void learned_apply(gkb_ctx* c, Inner<T>& in, const T* r_in, T* z_out, const PcgS
   for (int l = 0; l < net->L; ++l) {
     const uint16_t* w = net->wf + (size_t)l * net->taps * 256;
     const float* b = net->bias + 16 * l;
+    const int cin = net->ch[l];
     if (G.dim == 2) {
       if (l < net->L - 1)
-        k_conv<2, kOutReluBf16><<<blocks, 256, 0, s>>>(g, net->act[l], w, b, net->act[l + 1], nullptr, f1, f2);
+        launch_conv<2, kOutReluBf16>(cin, blocks, s, g, net->act[l], w, b, net->act[l + 1], nullptr, f1, f2);
       else
-        k_conv<2, kOutF32><<<blocks, 256, 0, s>>>(g, net->act[l], w, b, net->y16, nullptr, f1, f2);
+        launch_conv<2, kOutF32>(cin, blocks, s, g, net->act[l], w, b, net->y16, nullptr, f1, f2);
     } else {
       if (l < net->L - 1)
-        k_conv<3, kOutReluBf16><<<blocks, 256, 0, s>>>(g, net->act[l], w, b, net->act[l + 1], nullptr, f1, f2);
+        launch_conv<3, kOutReluBf16>(cin, blocks, s, g, net->act[l], w, b, net->act[l + 1], nullptr, f1, f2);
       else
-        k_conv<3, kOutF32><<<blocks, 256, 0, s>>>(g, net->act[l], w, b, net->y16, nullptr, f1, f2);
+        launch_conv<3, kOutF32>(cin, blocks, s, g, net->act[l], w, b, net->y16, nullptr, f1, f2);
     }
   }
   // c (stored in z_out) with c.rt, then M c (into the rt buffer) with c.Mc,
