@@ -251,14 +251,25 @@ __global__ __launch_bounds__(256) void k_wgrad(CnnGeom g, const uint16_t* __rest
   for (int e = threadIdx.x; e < NP; e += 256) dst[e] = red[e];
 }
 
-// sum the block partials in a fixed order
+// Sum the block partials in a fixed order: a block takes 16 consecutive
+// outputs; its 16 thread groups sum the partials b = g, g + 16, ... of
+// them, and the 16 group sums are added in order.
+constexpr int kRedOut = 16;
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int nblk,
                                                       int np, float* __restrict__ out) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= np) return;
+  const int o = threadIdx.x % kRedOut, grp = threadIdx.x / kRedOut;
+  const int e = blockIdx.x * kRedOut + o;
   float s = 0.f;
-  for (int b = 0; b < nblk; ++b) s += part[(size_t)b * np + e];
-  out[e] = s;
+  if (e < np)
+    for (int b = grp; b < nblk; b += 256 / kRedOut) s += part[(size_t)b * np + e];
+  __shared__ float sh[256];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  if (grp == 0 && e < np) {
+    float t = 0.f;
+    for (int g = 0; g < 256 / kRedOut; ++g) t += sh[g * kRedOut + o];
+    out[e] = t;
+  }
 }
 
 // padded gradient [taps][ci][co] + db[co] -> flat layer layout W[tap][ci][co], b[co]
@@ -345,20 +356,25 @@ __global__ __launch_bounds__(256) void k_loss_part(long Pb, int c, const float* 
 }
 
 // mean squared error over all batch entries (scalar[0]) and the per-sample
-// weight 1 / (points * channels) (scalar[1 + s]) from the partials; inputs and
-// targets are already normalised by the residual scale
-__global__ __launch_bounds__(64) void k_loss_final(int batch, int nblk, long per_sample,
-                                                   const double* num, double* scal) {
-  if (threadIdx.x != 0) return;
+// weight 1 / (points * channels) (scalar[1 + s]) from the partials (one
+// block of 256 threads, fixed order); inputs and targets are already
+// normalised by the residual scale
+__global__ __launch_bounds__(256) void k_loss_final(int batch, int nblk, long per_sample,
+                                                    const double* num, double* scal) {
+  __shared__ double sh[4];
   double L = 0.0;
   const double inv = 1.0 / double(per_sample);
   for (int s = 0; s < batch; ++s) {
     double a = 0.0;
-    for (int k = 0; k < nblk; ++k) a += num[s * nblk + k];
-    scal[1 + s] = inv;
-    L += a * inv;
+    for (int k = threadIdx.x; k < nblk; k += 256) a += num[s * nblk + k];
+    a = block_sum<256>(a, sh);  // valid in thread 0
+    __syncthreads();            // sh is reused by the next sample
+    if (threadIdx.x == 0) {
+      scal[1 + s] = inv;
+      L += a * inv;
+    }
   }
-  scal[0] = L / batch;
+  if (threadIdx.x == 0) scal[0] = L / batch;
 }
 
 // dz = 2 (y - e) / (points * channels * batch), BF16 [P][16]
@@ -546,7 +562,8 @@ int cnn_backward_dim(gkb_cnn* n, const gkb::CnnGeom& g, float* dx16) {
       gkb::k_wgrad<DIM, 8><<<wblk, 256, 0, n->s>>>(g, n->act[l], dz, n->wpart);
     else
       gkb::k_wgrad<DIM, 16><<<wblk, 256, 0, n->s>>>(g, n->act[l], dz, n->wpart);
-    gkb::k_wgrad_reduce<<<(NP + 255) / 256, 256, 0, n->s>>>(n->wpart, wblk, NP, n->pad);
+    gkb::k_wgrad_reduce<<<(NP + gkb::kRedOut - 1) / gkb::kRedOut, 256, 0, n->s>>>(n->wpart, wblk,
+                                                                                 NP, n->pad);
     gkb::k_grad_flat<<<cnn_grid(TAPS * 256 + 16), 256, 0, n->s>>>(n->pad, TAPS, n->ch[l],
                                                                    n->ch[l + 1], n->grad + n->off[l]);
     const uint16_t* wd = n->wd + (size_t)l * TAPS * 256;
@@ -772,7 +789,7 @@ int gkb_cnn_train(gkb_cnn* n, const float* inputs, const float* targets, int n_p
     if (rc) return rc;
     gkb::k_loss_part<<<dim3(lblk, batch), 256, 0, n->s>>>(Pc, cout, n->y16, n->ebuf, n->lnum,
                                                           n->lden);
-    gkb::k_loss_final<<<1, 64, 0, n->s>>>(batch, lblk, Pc * cout, n->lnum, n->lscal);
+    gkb::k_loss_final<<<1, 256, 0, n->s>>>(batch, lblk, Pc * cout, n->lnum, n->lscal);
     gkb::k_loss_grad<<<cnn_grid(g.P * 16), 256, 0, n->s>>>(Pc, cout, batch, n->y16, n->ebuf,
                                                            n->lscal, n->dz0);
     rc = cnn_backward_act(n, g, nullptr);
@@ -812,7 +829,7 @@ int gkb_cnn_eval(gkb_cnn* n, const float* inputs, const float* targets, int n_pa
     gkb::k_loss_part<<<dim3(lblk, 1), 256, 0, n->s>>>(P, cout, n->y16,
                                                       targets + (size_t)k * P * cout, n->lnum,
                                                       n->lden);
-    gkb::k_loss_final<<<1, 64, 0, n->s>>>(1, lblk, P * cout, n->lnum, n->lscal);
+    gkb::k_loss_final<<<1, 256, 0, n->s>>>(1, lblk, P * cout, n->lnum, n->lscal);
     CNNCK(hipMemcpyAsync(hl, n->lscal, sizeof(double), hipMemcpyDeviceToHost, n->s));
     CNNCK(hipStreamSynchronize(n->s));
     total += hl[0];
