@@ -454,8 +454,13 @@ void vcycle(gkb_ctx* c, Inner<T>& in, int l, const T* b, T* x, double* dot_parti
     if (sm) k_restrict<T, 2, true><<<tg, kBlock, 0, s>>>(L.g, Lc.g, rsrc, Lc.b, st, Lc.dinv, omc, x0c);
     else k_restrict<T, 2, false><<<tg, kBlock, 0, s>>>(L.g, Lc.g, rsrc, Lc.b, st, Lc.dinv, omc, x0c);
   } else {
+    // fine v, w pairs (2i, 2i+1) aligned: even x extent and array offsets
+    // (FP32 only: the 16-byte FP64 pairs measured slower than two loads)
+    const int pair = sizeof(T) == 4 && L.g.n[0] % 2 == 0 && L.g.off[1] % 2 == 0 &&
+                     L.g.off[2] % 2 == 0;
     if (sm) k_restrict<T, 3, true><<<tg, kBlock, 0, s>>>(L.g, Lc.g, rsrc, Lc.b, st, Lc.dinv, omc, x0c);
-    else k_restrict<T, 3, false><<<tg, kBlock, 0, s>>>(L.g, Lc.g, rsrc, Lc.b, st, Lc.dinv, omc, x0c);
+    else k_restrict<T, 3, false><<<tg, kBlock, 0, s>>>(L.g, Lc.g, rsrc, Lc.b, st, Lc.dinv, omc, x0c,
+                                                        pair);
   }
   vcycle<T>(c, in, l + 1, Lc.b, Lc.x, nullptr, st, x0c != nullptr);
   // prolongate into the current iterate (or into a zeroed x when no pre-smoothing)

@@ -572,11 +572,27 @@ __device__ __forceinline__ double tan_weight(int t, int T, int nc, int lo, int h
 // the transposed weights.
 // x0c (optional): the coarse level's first smoothing sweep from a zero
 // guess, x0c = omega_c dinv_c bc, written in the same pass
+template <typename T>
+struct Pair2;
+template <>
+struct Pair2<float> {
+  typedef float2 type;
+};
+template <>
+struct Pair2<double> {
+  typedef double2 type;
+};
+
+// pair: the fine v and w faces 2i, 2i+1 of a row sit at an even (aligned)
+// index (x extent and array offsets even), so the DIV transfer in 3D loads
+// them as one pair (they share the mask of their normal index); the sum
+// keeps the order of the general loop below, so both give the same bits
 template <typename T, int DIM, int C, bool SM>
 __device__ __forceinline__ void restrict_face(const Grid& Gf, const Grid& Gc,
                                               const T* __restrict__ rf, T* __restrict__ bc,
                                               const T* __restrict__ dinv_c, T omega_c,
-                                              T* __restrict__ x0c, int idx, int k, int done) {
+                                              T* __restrict__ x0c, int idx, int k, int done,
+                                              int pair) {
   const int e0 = Gc.ext[C][0], e1 = Gc.ext[C][1];
   if (idx >= e0 * e1 || k >= Gc.ext[C][2]) return;
   const int j = idx / e0, i = idx - j * e0;
@@ -595,6 +611,49 @@ __device__ __forceinline__ void restrict_face(const Grid& Gf, const Grid& Gc,
   // fine rows per tangential axis: the two covered ones (DIV), with one
   // more on each side (SMOOTH)
   constexpr int kT = SM ? 4 : 2, kT0 = SM ? -1 : 0;
+  if constexpr (!SM && DIM == 3 && C != 0) {
+    if (pair) {  // uniform
+      // x is a tangential axis; B the other one (z for v, y for w).  The
+      // general loop runs (dn, A1, A2): for v A1 = z, A2 = x, for w A1 = x,
+      // A2 = y
+      constexpr int B = C == 1 ? 2 : 1;
+      typedef typename Pair2<T>::type T2;
+#pragma unroll
+      for (int dn = -1; dn <= 1; ++dn) {
+        const int fn = 2 * P[C] + dn;
+        if (fn < 0 || fn > nfC) continue;
+        const T wn = dn == 0 ? T(1) : T(0.5);
+        const bool on = unk<C>(Gf, fn);
+        T2 pb[2];
+#pragma unroll
+        for (int tb = 0; tb < 2; ++tb) {
+          int Q[3];
+          Q[C] = fn;
+          Q[0] = 2 * P[0];
+          Q[B] = 2 * P[B] + tb;
+          pb[tb] = on ? *reinterpret_cast<const T2*>(rf + fidx<C>(Gf, Q[0], Q[1], Q[2]))
+                      : T2{T(0), T(0)};
+        }
+        if (C == 1) {  // (z, x) order
+          acc += wn * pb[0].x;
+          acc += wn * pb[0].y;
+          acc += wn * pb[1].x;
+          acc += wn * pb[1].y;
+        } else {  // (x, y) order
+          acc += wn * pb[0].x;
+          acc += wn * pb[1].x;
+          acc += wn * pb[0].y;
+          acc += wn * pb[1].y;
+        }
+      }
+      const T dc = x0c ? dinv_c[f] : T(0);
+      if (done) return;
+      const T v = acc * T(0.125);
+      bc[f] = v;
+      if (x0c) x0c[f] = omega_c * dc * v;
+      return;
+    }
+  }
 #pragma unroll
   for (int dn = -1; dn <= 1; ++dn) {
     const int fn = 2 * P[C] + dn;
@@ -632,15 +691,16 @@ template <typename T, int DIM, bool SM>
 __global__ __launch_bounds__(kBlock) void k_restrict(Grid Gf, Grid Gc, const T* __restrict__ rf,
                                                      T* __restrict__ bc, const PcgState* st,
                                                      const T* __restrict__ dinv_c = nullptr,
-                                                     T omega_c = T(0), T* __restrict__ x0c = nullptr) {
+                                                     T omega_c = T(0), T* __restrict__ x0c = nullptr,
+                                                     int pair = 0) {
   // the flag is tested after the fine values are loaded
   const int done = st ? st->done : 0;
   const int c = blockIdx.z / Gc.nze;
   const int k = blockIdx.z - c * Gc.nze;
   const int idx = blockIdx.x * kBlock + threadIdx.x;
-  if (c == 0) restrict_face<T, DIM, 0, SM>(Gf, Gc, rf, bc, dinv_c, omega_c, x0c, idx, k, done);
-  else if (c == 1) restrict_face<T, DIM, 1, SM>(Gf, Gc, rf, bc, dinv_c, omega_c, x0c, idx, k, done);
-  else if (DIM == 3) restrict_face<T, DIM, 2, SM>(Gf, Gc, rf, bc, dinv_c, omega_c, x0c, idx, k, done);
+  if (c == 0) restrict_face<T, DIM, 0, SM>(Gf, Gc, rf, bc, dinv_c, omega_c, x0c, idx, k, done, pair);
+  else if (c == 1) restrict_face<T, DIM, 1, SM>(Gf, Gc, rf, bc, dinv_c, omega_c, x0c, idx, k, done, pair);
+  else if (DIM == 3) restrict_face<T, DIM, 2, SM>(Gf, Gc, rf, bc, dinv_c, omega_c, x0c, idx, k, done, pair);
 }
 
 // Prolongation + correction: fine faces coinciding with a coarse face take
