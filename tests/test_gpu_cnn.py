@@ -73,8 +73,10 @@ def _ref_backward_bf16(x, params, dim, channels, dy):
     return np.concatenate([v.reshape(-1) for dW, db in reversed(grads) for v in (dW, db)]), dx
 
 
+# every convolution variant: inputs of 2-4, 5-8 and 9-16 channels (channel
+# groups 4, 8, 16) forward and in the adjoint, in 2D and 3D
 CASES = [(2, (3, 16, 16, 16, 2), (2, 24, 40)), (3, (4, 8, 8, 3), (2, 12, 10, 17)),
-         (3, (4, 16, 3), (1, 9, 16, 33))]
+         (3, (4, 16, 3), (1, 9, 16, 33)), (2, (5, 8, 12, 2), (2, 20, 18))]
 
 
 @pytest.mark.parametrize("dim,channels,shape", CASES)
@@ -108,7 +110,7 @@ def test_forward_matches_reference(dim, channels, shape):
     assert np.abs(y1 - r1).max() <= 1e-5 * np.abs(r1).max()
 
 
-@pytest.mark.parametrize("dim,channels,shape", CASES[:2])
+@pytest.mark.parametrize("dim,channels,shape", CASES)
 def test_gradients_match_reference(dim, channels, shape):
     _say("cnn backward", dim, channels)
     import torch
